@@ -27,10 +27,10 @@ import time
 from collections import Counter
 
 from .. import codegen
-from . import features, knn, passes, space
+from . import features, gate, knn, passes, space
 from .evaluator import Evaluator
 
-STATUSES = ("ok", "compile_fail", "no_output", "load_fail", "wrong_output", "timeout", "crashed",
+STATUSES = ("ok", "compile_fail", "no_output", "gated", "load_fail", "wrong_output", "timeout", "crashed",
             "broken_report", "error")
 
 
@@ -115,6 +115,11 @@ def _build(v: space.Variant, workdir):
     except Exception as e:      # noqa: BLE001
         return dict(kind="compile", family=v.family, key=v.key(), variant=v.to_json(), status="compile_fail",
                     stage="driver", detail=f"{type(e).__name__}: {e}"[-300:], seconds=round(time.time() - t0, 2))
+    reason = gate.check(b.code)
+    if reason:
+        # built, but never handed to the GPU (see tuner/gate.py)
+        return dict(kind="compile", family=v.family, key=v.key(), variant=v.to_json(), status="gated",
+                    stage="gate", sha=b.code_hash, detail=reason[-300:], seconds=round(time.time() - t0, 2))
     p = _co_path(workdir, v.family, b.code_hash)
     os.makedirs(os.path.dirname(p), exist_ok=True)
     if not os.path.exists(p):

@@ -212,14 +212,14 @@ class RandomOrdersDisabled(RuntimeError):
 
 @dataclass
 class PipelineMix:
-    """Shares of the pipeline sample.
+    """Shares of the knob exploration's pipeline sample.
 
-    Random phase orders (the paper's Sec. 3 kind, alone or after -O3) are
-    off by default: one of them built a code object that took a GPU memory
-    aperture violation, with no defect found in the kernel source, so
-    explorations that run candidates on the GPU use LLVM's standard
-    pipelines and the flags of their passes only.  The generator remains for
-    CPU-side use (`allow_random_orders=True`)."""
+    The knob exploration pairs each knob draw with a standard pipeline (some
+    with flags of their passes); its sample, and the tuning table measured
+    from it, stay fixed.  Random phase orders (the paper's Sec. 3 kind, alone
+    or after -O3) are explored on fixed knobs by `tuner.orders`, where every
+    code object passes the gate of `tuner.gate` before it runs.  Mixing them
+    into this sample needs `allow_random_orders=True`."""
     o3: float = 0.45              # the standard -O3 pipeline, default flags
     other_levels: float = 0.15    # -O1/-O2/-Os/-Oz
     flagged: float = 0.40         # -O3 with sampled opt/llc flags
@@ -246,7 +246,7 @@ def sample_pipelines(pool: list[str], count: int, seed: int, mix: PipelineMix = 
     `pool` holds wrapped pass strings (e.g. "function(gvn)"); a random phase
     order draws 1..max_len of them uniformly with repetition."""
     if (mix.random_order > 0 or mix.o3_suffix > 0) and not allow_random_orders:
-        raise RandomOrdersDisabled("random phase orders are switched off for GPU evaluation")
+        raise RandomOrdersDisabled("random phase orders are not part of the knob exploration's sample")
     rng = random.Random(f"{seed}:pipelines")
     out = []
     edges = [mix.o3, mix.other_levels, mix.flagged, mix.random_order, mix.o3_suffix]

@@ -32,6 +32,7 @@ import torch
 
 from .. import api, synth, workloads as W
 from ..timing import per_launch_ms
+from . import gate
 
 DEV = "cuda:0"
 ROTATE_BYTES = 640 << 20
@@ -336,6 +337,9 @@ class Worker:
             vid = self.default_vid
             loaded = False
             if code != "default":
+                reason = gate.check_file(code)
+                if reason:
+                    return dict(status="gated", detail=reason[:300])
                 try:
                     with open(code, "rb") as f:
                         vid = self.ctx.variant_load(f.read())

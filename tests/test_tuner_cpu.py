@@ -331,3 +331,83 @@ def test_best_so_far_counts_sampled_variants_in_order(tmp_path):
         db.add(dict(kind="eval", family="gemv", sha=f"s{i}", status="ok", times={"4096": 1.0 / sp}))
     b = P.best_so_far(db, "gemv", 4096, counts=(1, 3, 5, 6), samples=6, pool=pool)
     assert b == {1: 0.5, 3: 2.0, 5: 4.0, 6: 4.0}
+
+
+# ---------------------------------------------------------------- code-object gate --
+
+DATA = os.path.join(HERE, "data")
+
+
+def _llc_asm(ll_text, tmp_path, name):
+    src = tmp_path / f"{name}.ll"
+    src.write_text(ll_text)
+    out = tmp_path / f"{name}.s"
+    import subprocess
+    subprocess.run([codegen.tool("llc"), "-mtriple=amdgcn-amd-amdhsa", f"-mcpu={codegen.ARCH}", "-O3",
+                    str(src), "-o", str(out)], check=True, capture_output=True)
+    return out.read_text()
+
+
+def _insts(asm):
+    return [ln.split(";")[0].split()[:1] + [x.strip() for x in " ".join(ln.split(";")[0].split()[1:]).split(",")]
+            for ln in asm.splitlines() if ln.startswith("\t") and not ln.strip().startswith(".")]
+
+
+def test_backend_drops_the_carry_of_a_flat_stack_address(tmp_path):
+    """The cause of the aperture violation some random orders produced: the flat address
+    (private aperture + frame offset 0x60) - 4 comes out with its high half one too low."""
+    ll = open(os.path.join(DATA, "aperture_carry.ll")).read()
+    ins = _insts(_llc_asm(ll, tmp_path, "stack"))
+    base = next(i for i in ins if i[0] == "s_mov_b64" and i[2] == "src_private_base")
+    hi_reg = "s" + str(int(base[1][2:].split(":")[0]) + 1)         # s[a:b] -> the high half sb
+    lo = next(i for i in ins if i[0] == "s_add_u32" and i[3] == "0x5c")
+    hi = next(i for i in ins if i[0] == "s_addc_u32" and i[2] == hi_reg)
+    # the low add cannot carry (0 + 0x5c) while the high add subtracts one (+0xffffffff + carry)
+    assert lo[2] == "0" and hi[3] == "-1"
+    # the same arithmetic on an LDS array keeps the carry: 0x60 + -4 in the low add
+    lds = ll.replace("%pad = alloca [24 x i32], align 16, addrspace(5)", "") \
+        .replace("%a = alloca [4 x float], align 16, addrspace(5)", "") \
+        .replace("addrspace(5) %pad", "addrspace(3) @pad").replace("addrspace(5) %a", "addrspace(3) @a") \
+        .replace("target triple = \"amdgcn-amd-amdhsa\"",
+                 "target triple = \"amdgcn-amd-amdhsa\"\n@pad = internal addrspace(3) global [24 x i32] poison, "
+                 "align 16\n@a = internal addrspace(3) global [4 x float] poison, align 16")
+    ins = _insts(_llc_asm(lds, tmp_path, "lds"))
+    assert any(i[0] == "s_mov_b64" and i[2] == "src_shared_base" for i in ins)
+    assert any(i[0] == "s_add_u32" and i[2:4] == ["0x60", "-4"] for i in ins)
+
+
+def test_gate_rejects_flat_stack_addresses(tmp_path):
+    import subprocess
+    from paper_1810_10496_amd.tuner import gate
+    obj, co = tmp_path / "k.o", tmp_path / "k.co"
+    subprocess.run([codegen.tool("llc"), "-mtriple=amdgcn-amd-amdhsa", f"-mcpu={codegen.ARCH}", "-O3",
+                    "-filetype=obj", os.path.join(DATA, "aperture_carry.ll"), "-o", str(obj)], check=True)
+    subprocess.run([codegen.tool("ld.lld"), "-shared", str(obj), "-o", str(co)], check=True)
+    reason = gate.check_file(str(co))
+    assert reason and "src_private_base" in reason and " k" in reason
+
+
+def test_gate_rejects_the_order_that_faulted_and_passes_standard_builds():
+    """The 44-pass random order whose gemv_t code object stopped the GPU queue (knobs
+    ROWS 64, WAVES 8, VEC 4, UNROLL 4; reconstructed from the seeded sampler) is rejected;
+    every family's default and a flagged standard build pass."""
+    from paper_1810_10496_amd.tuner import gate
+    v = space.Variant.from_json(json.load(open(os.path.join(DATA, "aperture_fault_variant.json"))))
+    assert v.pipeline.count(",") + 1 == 44 and "amdgpu-attributor" in v.pipeline and "sroa" not in v.pipeline
+    b = codegen.compile_variant(v.family, v.knobs, v.pipeline, tuple(v.llc_flags))
+    reason = gate.check(b.code)
+    assert reason and "pk_gemvt_partial" in reason
+    b = codegen.compile_variant(v.family, v.knobs, "default<O3>", ("-O3", "-misched=gcn-max-ilp"))
+    assert gate.check(b.code) is None
+    build = os.path.join(os.path.dirname(HERE), "paper_1810_10496_amd", "_build")
+    for fam in codegen.FAMILIES:
+        p = os.path.join(build, f"{fam}.co")
+        if os.path.exists(p):
+            assert gate.check_file(p) is None, fam
+
+
+def test_gated_build_is_recorded_and_never_written(tmp_path):
+    v = space.Variant.from_json(json.load(open(os.path.join(DATA, "aperture_fault_variant.json"))))
+    rec = X._build(v, str(tmp_path))
+    assert rec["status"] == "gated" and rec["stage"] == "gate" and "src_private_base" in rec["detail"]
+    assert not os.path.exists(X._co_path(str(tmp_path), v.family, rec["sha"]))

@@ -464,33 +464,60 @@ void oracle_mvt(int64_t N, const float *A, int64_t lda, const float *y1, const f
  *   ey[0][j]  = fict[t]                                         (all j)
  *   ey[i][j] -= 0.5 (hz[i][j] - hz[i-1][j])                     (i >= 1)
  *   ex[i][j] -= 0.5 (hz[i][j] - hz[i][j-1])                     (j >= 1)
- *   hz[i][j] -= 0.7 (ex[i][j+1] - ex[i][j] + ey[i+1][j] - ey[i][j])
+ *   hz[i][j] -= c (ex[i][j+1] - ex[i][j] + ey[i+1][j] - ey[i][j])
  *                                                   (i < NX-1, j < NY-1)
+ * with c = 0.7 as the FP32 value the GPU multiplies by, widened.
  * Fields are updated in place (inputs are copied to the double outputs first).
+ * If sex/sey/shz are not NULL they receive each element's error scale: the sum
+ * of the magnitudes of the terms of the last update applied to it (for ey[i][j]:
+ * |ey| + 0.5(|hz[i][j]| + |hz[i-1][j]|) with the values that update read), or
+ * the element's own magnitude where no update ever touched it.
  * ------------------------------------------------------------------------ */
 void oracle_fdtd2d(int64_t T, int64_t NX, int64_t NY, const float *fict, const float *ex0,
-                   const float *ey0, const float *hz0, double *ex, double *ey, double *hz)
+                   const float *ey0, const float *hz0, double *ex, double *ey, double *hz,
+                   double *sex, double *sey, double *shz)
 {
+    const double c = (double)0.7f;
+    const int scales = sex != NULL && sey != NULL && shz != NULL;
     for (int64_t i = 0; i < NX * NY; ++i) {
         ex[i] = (double)ex0[i];
         ey[i] = (double)ey0[i];
         hz[i] = (double)hz0[i];
+        if (scales) {
+            sex[i] = fabs(ex[i]);
+            sey[i] = fabs(ey[i]);
+            shz[i] = fabs(hz[i]);
+        }
     }
     for (int64_t t = 0; t < T; ++t) {
-        for (int64_t j = 0; j < NY; ++j)
+        for (int64_t j = 0; j < NY; ++j) {
             ey[j] = (double)fict[t];
+            if (scales)
+                sey[j] = fabs(ey[j]);
+        }
 #pragma omp parallel for schedule(static)
         for (int64_t i = 1; i < NX; ++i)
-            for (int64_t j = 0; j < NY; ++j)
-                ey[i * NY + j] -= 0.5 * (hz[i * NY + j] - hz[(i - 1) * NY + j]);
+            for (int64_t j = 0; j < NY; ++j) {
+                const int64_t o = i * NY + j;
+                if (scales)
+                    sey[o] = fabs(ey[o]) + 0.5 * (fabs(hz[o]) + fabs(hz[o - NY]));
+                ey[o] -= 0.5 * (hz[o] - hz[o - NY]);
+            }
 #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < NX; ++i)
-            for (int64_t j = 1; j < NY; ++j)
-                ex[i * NY + j] -= 0.5 * (hz[i * NY + j] - hz[i * NY + j - 1]);
+            for (int64_t j = 1; j < NY; ++j) {
+                const int64_t o = i * NY + j;
+                if (scales)
+                    sex[o] = fabs(ex[o]) + 0.5 * (fabs(hz[o]) + fabs(hz[o - 1]));
+                ex[o] -= 0.5 * (hz[o] - hz[o - 1]);
+            }
 #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < NX - 1; ++i)
-            for (int64_t j = 0; j < NY - 1; ++j)
-                hz[i * NY + j] -= 0.7 * (ex[i * NY + j + 1] - ex[i * NY + j] +
-                                         ey[(i + 1) * NY + j] - ey[i * NY + j]);
+            for (int64_t j = 0; j < NY - 1; ++j) {
+                const int64_t o = i * NY + j;
+                if (scales)
+                    shz[o] = fabs(hz[o]) + c * (fabs(ex[o + 1]) + fabs(ex[o]) + fabs(ey[o + NY]) + fabs(ey[o]));
+                hz[o] -= c * (ex[o + 1] - ex[o] + ey[o + NY] - ey[o]);
+            }
     }
 }

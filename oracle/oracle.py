@@ -70,7 +70,8 @@ def _load():
     lib.oracle_syr2k.argtypes = [_i64, _i64, _f32, _f32p, _i64, _f32p, _i64, _f32, _f32p, _i64, _f64p]
     lib.oracle_gesummv.argtypes = [_i64, _f32, _f32p, _i64, _f32, _f32p, _i64, _f32p, _f64p]
     lib.oracle_mvt.argtypes = [_i64, _f32p, _i64, _f32p, _f32p, _f32p, _f32p, _f64p, _f64p]
-    lib.oracle_fdtd2d.argtypes = [_i64, _i64, _i64, _f32p, _f32p, _f32p, _f32p, _f64p, _f64p, _f64p]
+    lib.oracle_fdtd2d.argtypes = [_i64, _i64, _i64, _f32p, _f32p, _f32p, _f32p, _f64p, _f64p, _f64p,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     _lib = lib
     return lib
 
@@ -251,15 +252,16 @@ def mvt(A, y1, y2, x1, x2):
     return o1, o2
 
 
-def fdtd2d(fict, ex, ey, hz):
-    """T = len(fict) steps of the 2D FDTD update; returns (ex, ey, hz) in FP64."""
+def fdtd2d(fict, ex, ey, hz, with_scale: bool = False):
+    """T = len(fict) steps of the 2D FDTD update; returns (ex, ey, hz) in FP64.  With
+    `with_scale`, also each element's error scale (ex, ey, hz): the summed magnitudes
+    of the terms of the last update that wrote it, or |value| if none did."""
     fict, ex, ey, hz = (_c32(v) for v in (fict, ex, ey, hz))
     NX, NY = ex.shape
-    oex = np.empty((NX, NY), np.float64)
-    oey = np.empty((NX, NY), np.float64)
-    ohz = np.empty((NX, NY), np.float64)
-    _load().oracle_fdtd2d(len(fict), NX, NY, fict, ex, ey, hz, oex, oey, ohz)
-    return oex, oey, ohz
+    out = [np.empty((NX, NY), np.float64) for _ in range(6 if with_scale else 3)]
+    sc = [o.ctypes.data for o in out[3:]] if with_scale else [None, None, None]
+    _load().oracle_fdtd2d(len(fict), NX, NY, fict, ex, ey, hz, *out[:3], *sc)
+    return (tuple(out[:3]), tuple(out[3:])) if with_scale else tuple(out)
 
 
 def max_err(gpu, ref, scale=None):

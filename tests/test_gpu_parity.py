@@ -461,6 +461,10 @@ def test_graph_replay_matches_eager(ctx):
     eo = ctx.conv2d(gg, taps)
     torch.cuda.synchronize()
     eC, e1, e2, eo = h(eC), h(e1), h(e2), h(eo)
+    # the eager results (which every replay must reproduce bit for bit) against the oracle
+    assert o.max_err(eC, o.gemm(A, B, C, alpha, beta), o.gemm_scale(A, B, C, alpha, beta)) <= 1e-4
+    assert o.max_err(e1, o.gemv(Av, x)) <= 1e-4 and o.max_err(e2, o.gemv_t(Av, z)) <= 1e-4
+    assert o.max_err(eo, o.conv2d(grid, taps), o.conv2d(np.abs(grid), np.abs(taps))) <= 1e-4
     for rep in range(4):
         with torch.cuda.stream(s):
             Cg.copy_(C0)

@@ -2,7 +2,13 @@
 its instance (same inputs, same calls) with the variants the tuning table selects,
 checked against the FP64 oracle -- in full where the oracle is cheap, otherwise on
 sampled rows (products) or sampled column sets (correlation, covariance, SYRK),
-whose outputs depend on the sampled rows/columns only."""
+whose outputs depend on the sampled rows/columns only.
+
+Covered: every batch instance at all five sizes with the table's variants; every
+non-default feature-reuse assignment (K = 1 and 3) on the instances it serves; the
+replayed graph of the tuned batch at 256, 512 and 1000 (each instance against the
+oracle after the first replay, and bitwise equal after the second); the precision
+workloads and the next rows."""
 import numpy as np
 import pytest
 import torch
@@ -34,7 +40,7 @@ def _sample(n, k, seed):
 
 
 def _instances():
-    out = W.batch_instances((1000, 4096)) + W.config_instances() + W.precision_instances((4096,)) + \
+    out = W.batch_instances(W.SIZES) + W.config_instances() + W.precision_instances((4096,)) + \
         W.corr_precision_instances((4096,)) + W.next_instances()
     seen, uniq = set(), []
     for i in out:
@@ -61,11 +67,10 @@ def _run(ctx, inst):
     return st, {k: h(v) for k, v in before.items()}
 
 
-@pytest.mark.parametrize("inst", INSTANCES, ids=[i.name for i in INSTANCES])
-def test_tuned_workload_vs_oracle(ctx, inst):
-    print("[case] tuned", inst.name, flush=True)
+def check(inst, st, x):
+    """(error, tolerance) of the instance's outputs in `st` against the oracle on the
+    inputs `x` (host copies taken before the run)."""
     op, n, prec = inst.op, inst.size, _prec(inst.name)
-    st, x = _run(ctx, inst)
     tol = TOL[prec]
     if op.startswith("gemm3"):
         rows = _sample(n, 16, 7001)
@@ -131,13 +136,111 @@ def test_tuned_workload_vs_oracle(ctx, inst):
         err = max(o.max_err(h(st["x1"]), r1, s1), o.max_err(h(st["x2"]), r2, s2))
     elif op == "fdtd2d":
         T = x["fict"].shape[0]
-        refs = o.fdtd2d(x["fict"], x["ex"], x["ey"], x["hz"])
-        err = 0.0
-        for key, ref in zip(("ex", "ey", "hz"), refs):
-            d = np.abs(h(st[key][0]).astype(np.float64) - ref)
-            err = max(err, float(np.max(d)) / max(1.0, float(np.max(np.abs(ref)))))
-        tol = 1e-6 * (1 + T)
+        refs, scales = o.fdtd2d(x["fict"], x["ex"], x["ey"], x["hz"], with_scale=True)
+        err = max(o.max_err(h(st[key][0]), ref, sc) for key, ref, sc in zip(("ex", "ey", "hz"), refs, scales))
+        tol = 1e-6 * (1 + T)    # per element, against the magnitudes of its last update's terms
     else:
         raise AssertionError(f"no check for {inst.name}")
+    return err, tol
+
+
+@pytest.mark.parametrize("inst", INSTANCES, ids=[i.name for i in INSTANCES])
+def test_tuned_workload_vs_oracle(ctx, inst):
+    print("[case] tuned", inst.name, flush=True)
+    st, x = _run(ctx, inst)
+    err, tol = check(inst, st, x)
     print("[case] tuned", inst.name, "err", err, flush=True)
     assert err <= tol
+
+
+# ------------------------------------------------------------------ feature reuse --
+
+def _reuse_cases():
+    """(instance, K) for every batch instance one of whose families has a non-default
+    reuse assignment at its size."""
+    nondef = {(e["family"], int(e["size"]), int(e["k"])) for e in tuned.read_reuse() if not e.get("is_default")}
+    out = []
+    for inst in W.batch_instances(W.SIZES):
+        for k in (1, 3):
+            if any((f, inst.size, k) in nondef for f in inst.families):
+                out.append((inst, k))
+    return out
+
+
+REUSE = _reuse_cases()
+
+
+@pytest.fixture(scope="module")
+def reuse(ctx):
+    return tuned.load_reuse(ctx)
+
+
+def test_every_reuse_assignment_is_exercised():
+    """Each non-default assignment is reachable through an instance of the batch."""
+    want = {(e["family"], int(e["size"]), int(e["k"])) for e in tuned.read_reuse() if not e.get("is_default")}
+    got = {(f, inst.size, k) for inst, k in REUSE for f in inst.families}
+    assert want <= got
+
+
+@pytest.mark.parametrize("inst,k", REUSE, ids=[f"{i.name}-k{k}" for i, k in REUSE])
+def test_reuse_variant_vs_oracle(ctx, reuse, inst, k):
+    print("[case] reuse", inst.name, "K", k, flush=True)
+    vids = {f: reuse.get((f, inst.size, k)) for f in inst.families}
+    assert all(v is not None for v in vids.values()), "a reuse code object could not be loaded"
+    for f, v in vids.items():
+        ctx.variant_select(f, v)
+    try:
+        st, x = _run(ctx, inst)
+    finally:
+        for f in vids:
+            ctx.variant_select(f, -1)
+    err, tol = check(inst, st, x)
+    print("[case] reuse", inst.name, "K", k, "err", err, flush=True)
+    assert err <= tol
+
+
+# --------------------------------------------------------- the replayed tuned batch --
+
+def test_tuned_batch_graph_vs_oracle(ctx):
+    """The batch at 256, 512 and 1000 captured into one graph with the table's variants
+    (as the benchmark captures it), replayed: every instance against the oracle after the
+    first replay; after restoring the in-place operands and doing eager work, a second
+    replay gives the same bits."""
+    insts = W.batch_instances((256, 512, 1000))
+    stream = torch.cuda.Stream()
+    states, before = [], []
+    for inst in insts:
+        st = inst.make(DEV, 1)
+        states.append(st)
+        before.append({k: (v[0].clone() if isinstance(v, list) else v.clone())
+                       for k, v in st.items() if isinstance(v, (list, torch.Tensor)) and k != "ws"})
+    torch.cuda.synchronize()
+    with ctx.capture(stream) as graph:
+        for inst, st in zip(insts, states):
+            inst.run(ctx, st, 0, stream)
+    print(f"[case] tuned batch graph of {len(insts)} instances captured", flush=True)
+
+    def outputs(st):
+        return {k: h(v[0] if isinstance(v, list) else v) for k, v in st.items()
+                if isinstance(v, (list, torch.Tensor)) and k != "ws"}
+
+    graph.launch(stream)
+    stream.synchronize()
+    first = []
+    for inst, st, b in zip(insts, states, before):
+        x = {k: h(v) for k, v in b.items()}
+        err, tol = check(inst, st, x)
+        print("[case] graph", inst.name, "err", err, flush=True)
+        assert err <= tol, inst.name
+        first.append(outputs(st))
+    for st, b in zip(states, before):         # in-place operands (C, D) back to their inputs
+        for k, v in b.items():
+            (st[k][0] if isinstance(st[k], list) else st[k]).copy_(v)
+    torch.ones(1 << 20, device=DEV).mul_(2.0)  # eager work between the replays
+    torch.cuda.synchronize()
+    graph.launch(stream)
+    stream.synchronize()
+    for inst, st, f in zip(insts, states, first):
+        for k, v in outputs(st).items():
+            assert np.array_equal(v, f[k]), (inst.name, k)
+    graph.destroy()

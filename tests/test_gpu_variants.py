@@ -9,12 +9,14 @@ import torch
 
 from oracle import oracle as o
 from paper_1810_10496_amd import api, codegen, synth
+from paper_1810_10496_amd.tuner import gate
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 TAPS2 = np.array(synth.CONV2D_TAPS, np.float32)
 
-# a random phase order from the pass pool (fixed here so the test is stable)
+# a random phase order from the pass pool (fixed here so the test is stable); like every
+# random order it reaches the GPU only through the code-object gate (tuner/gate.py)
 ORDER = ("function(sroa),always-inline,function(instcombine<no-verify-fixpoint>),"
          "function(loop-mssa(licm)),function(gvn),function(simplifycfg),function(loop-unroll),"
          "function(infer-address-spaces),function(dse),function(slp-vectorizer)")
@@ -185,6 +187,7 @@ def check(ctx, family):
 def test_variant_vs_oracle(built, i):
     fam, knobs, pipe = VARIANTS[i]
     print("[case] variant", fam, knobs, pipe[:40], flush=True)
+    assert gate.check(built[i].code) is None
     ctx = api.context(0)
     vid = ctx.variant_load(built[i].code)
     f, k, _ = ctx.variant_info(vid)

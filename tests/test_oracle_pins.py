@@ -480,6 +480,9 @@ def test_fdtd_is_linear():
         assert np.max(np.abs(q - 2 * p)) < 1e-12
 
 
+C07 = float(np.float32(0.7))     # the GPU multiplies by the FP32 value of 0.7
+
+
 def test_fdtd_single_step_light_cone_pins_signs_and_offsets():
     # one hz impulse, everything else zero, one step: the update rules fix where
     # (and with which sign and weight) the impulse appears
@@ -499,9 +502,64 @@ def test_fdtd_single_step_light_cone_pins_signs_and_offsets():
     want_hz = np.zeros((NX, NY))
     for i in range(NX - 1):
         for j in range(NY - 1):
-            want_hz[i, j] = hz0[i, j] - 0.7 * (want_ex[i, j + 1] - want_ex[i, j] + want_ey[i + 1, j] - want_ey[i, j])
+            want_hz[i, j] = hz0[i, j] - C07 * (want_ex[i, j + 1] - want_ex[i, j] + want_ey[i + 1, j] - want_ey[i, j])
     want_hz[NX - 1, :] = hz0[NX - 1, :]
     want_hz[:, NY - 1] = hz0[:, NY - 1]
     assert np.max(np.abs(hz - want_hz)) < 1e-15
     assert hz[p, q] == pytest.approx(1.0 - 0.7 * 2.0)          # -(-0.5) - (-0.5): both neighbours pull
+    assert hz[p, q] == 1.0 - C07 * 2.0                          # with the FP32 coefficient the GPU uses
     assert np.count_nonzero(hz) == 5
+
+
+def test_fdtd_scales_light_cone_and_bound():
+    """Error scales of the FDTD oracle: after one step from a single hz impulse the scale
+    is non-zero exactly where an update read the impulse (0.5 on ey at (p, q) and (p+1, q),
+    on ex at (p, q) and (p, q+1); |hz| + c x the magnitudes around it on hz), and on random
+    fields it bounds |r| everywhere and the error of an FP32 evaluation element by element."""
+    NX, NY, p, q = 7, 8, 3, 4
+    z = np.zeros((NX, NY), np.float32)
+    hz0 = z.copy()
+    hz0[p, q] = 1.0
+    (ex, ey, hz), (sx, sy, sh) = o.fdtd2d(np.zeros(1, np.float32), z, z, hz0, with_scale=True)
+    want = np.zeros((NX, NY))
+    want[p, q] = want[p + 1, q] = 0.5
+    assert np.array_equal(sy, want)
+    want = np.zeros((NX, NY))
+    want[p, q] = want[p, q + 1] = 0.5
+    assert np.array_equal(sx, want)
+    # hz at (p, q) read ex (p, q), (p, q+1) and ey (p, q), (p+1, q), each 0.5 in magnitude
+    assert sh[p, q] == 1.0 + C07 * 2.0
+    assert sh[p - 1, q] == C07 * 0.5 and sh[p, q - 1] == C07 * 0.5
+    assert np.count_nonzero(sh) == 5
+    # random fields, several steps: |r| <= s, and a float32 evaluation stays within a few
+    # roundings per step of s (it would not if the scale dropped a term somewhere)
+    T = 8
+    fict, ex0, ey0, hz0 = _fdtd_inputs(31, 29, T, 341)
+    refs, scales = o.fdtd2d(fict, ex0, ey0, hz0, with_scale=True)
+    for r, sc in zip(refs, scales):
+        assert np.all(np.abs(r) <= sc * (1 + 1e-15))
+    ex, ey, hz = (v.astype(np.float32).copy() for v in (ex0, ey0, hz0))
+    half, c = np.float32(0.5), np.float32(0.7)
+    for t in range(T):
+        ey[0, :] = fict[t]
+        ey[1:, :] -= half * (hz[1:, :] - hz[:-1, :])
+        ex[:, 1:] -= half * (hz[:, 1:] - hz[:, :-1])
+        hz[:-1, :-1] -= c * (ex[:-1, 1:] - ex[:-1, :-1] + ey[1:, :-1] - ey[:-1, :-1])
+    errs = [o.max_err(g, r, sc) for g, r, sc in zip((ex, ey, hz), refs, scales)]
+    assert 0 < max(errs) <= 1e-6 * (1 + T), errs
+
+
+def test_gemm_split3_drops_exactly_the_lo_lo_term():
+    """a = b = 1 + 2^-9: hi = 1 (RNE to 8 significant bits), lo = 2^-9, so the three-term
+    product is 1 + 2^-8 and the dropped lo*lo is 2^-18 (the full product is 1 + 2^-8 + 2^-18)."""
+    a = np.array([[1.0 + 2.0 ** -9]], np.float32)
+    hi, lo = o.split_bf16(a)
+    assert hi[0, 0] == 1.0 and lo[0, 0] == 2.0 ** -9
+    got = o.gemm_split3(a, a, np.zeros((1, 1), np.float32), 1.0, 0.0)
+    assert got[0, 0] == 1.0 + 2.0 ** -8
+    assert o.gemm(a, a, np.zeros((1, 1), np.float32), 1.0, 0.0)[0, 0] == 1.0 + 2.0 ** -8 + 2.0 ** -18
+    # accumulated over K: each product drops its own lo*lo
+    K = 6
+    A = np.full((1, K), 1.0 + 2.0 ** -9, np.float32)
+    B = np.full((K, 1), 1.0 + 2.0 ** -9, np.float32)
+    assert o.gemm_split3(A, B, np.zeros((1, 1), np.float32), 1.0, 0.0)[0, 0] == K * (1.0 + 2.0 ** -8)

@@ -468,10 +468,14 @@ void oracle_mvt(int64_t N, const float *A, int64_t lda, const float *y1, const f
  *                                                   (i < NX-1, j < NY-1)
  * with c = 0.7 as the FP32 value the GPU multiplies by, widened.
  * Fields are updated in place (inputs are copied to the double outputs first).
- * If sex/sey/shz are not NULL they receive each element's error scale: the sum
- * of the magnitudes of the terms of the last update applied to it (for ey[i][j]:
- * |ey| + 0.5(|hz[i][j]| + |hz[i-1][j]|) with the values that update read), or
- * the element's own magnitude where no update ever touched it.
+ * If sex/sey/shz are not NULL they receive each element's error scale.  An
+ * update's own scale is the sum of the magnitudes of its terms (for ey[i][j]:
+ * |ey| + 0.5(|hz[i][j]| + |hz[i-1][j]|), with the values it read).  A rounding
+ * error committed anywhere travels on through every later update that reads
+ * the element, so an element's error scale is the largest own scale of any
+ * update in its domain of dependence: the maximum of its update's own scale and
+ * the error scales of the elements that update read.  The initial values (and
+ * the source assignments of row 0 of ey) carry their own magnitudes.
  * ------------------------------------------------------------------------ */
 void oracle_fdtd2d(int64_t T, int64_t NX, int64_t NY, const float *fict, const float *ex0,
                    const float *ey0, const float *hz0, double *ex, double *ey, double *hz,
@@ -500,7 +504,8 @@ void oracle_fdtd2d(int64_t T, int64_t NX, int64_t NY, const float *fict, const f
             for (int64_t j = 0; j < NY; ++j) {
                 const int64_t o = i * NY + j;
                 if (scales)
-                    sey[o] = fabs(ey[o]) + 0.5 * (fabs(hz[o]) + fabs(hz[o - NY]));
+                    sey[o] = fmax(fmax(fabs(ey[o]) + 0.5 * (fabs(hz[o]) + fabs(hz[o - NY])), sey[o]),
+                                  fmax(shz[o], shz[o - NY]));
                 ey[o] -= 0.5 * (hz[o] - hz[o - NY]);
             }
 #pragma omp parallel for schedule(static)
@@ -508,15 +513,19 @@ void oracle_fdtd2d(int64_t T, int64_t NX, int64_t NY, const float *fict, const f
             for (int64_t j = 1; j < NY; ++j) {
                 const int64_t o = i * NY + j;
                 if (scales)
-                    sex[o] = fabs(ex[o]) + 0.5 * (fabs(hz[o]) + fabs(hz[o - 1]));
+                    sex[o] = fmax(fmax(fabs(ex[o]) + 0.5 * (fabs(hz[o]) + fabs(hz[o - 1])), sex[o]),
+                                  fmax(shz[o], shz[o - 1]));
                 ex[o] -= 0.5 * (hz[o] - hz[o - 1]);
             }
 #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < NX - 1; ++i)
             for (int64_t j = 0; j < NY - 1; ++j) {
                 const int64_t o = i * NY + j;
-                if (scales)
-                    shz[o] = fabs(hz[o]) + c * (fabs(ex[o + 1]) + fabs(ex[o]) + fabs(ey[o + NY]) + fabs(ey[o]));
+                if (scales) {
+                    const double own = fabs(hz[o]) + c * (fabs(ex[o + 1]) + fabs(ex[o]) + fabs(ey[o + NY]) + fabs(ey[o]));
+                    const double rd = fmax(fmax(sex[o + 1], sex[o]), fmax(sey[o + NY], sey[o]));
+                    shz[o] = fmax(fmax(own, shz[o]), rd);
+                }
                 hz[o] -= c * (ex[o + 1] - ex[o] + ey[o + NY] - ey[o]);
             }
     }

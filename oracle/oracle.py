@@ -254,8 +254,10 @@ def mvt(A, y1, y2, x1, x2):
 
 def fdtd2d(fict, ex, ey, hz, with_scale: bool = False):
     """T = len(fict) steps of the 2D FDTD update; returns (ex, ey, hz) in FP64.  With
-    `with_scale`, also each element's error scale (ex, ey, hz): the summed magnitudes
-    of the terms of the last update that wrote it, or |value| if none did."""
+    `with_scale`, also each element's error scale (ex, ey, hz): the largest summed
+    term magnitude of any update in the element's domain of dependence (its own
+    update's and, through the values that update read, every earlier one's), since a
+    rounding error travels on through every update that reads it."""
     fict, ex, ey, hz = (_c32(v) for v in (fict, ex, ey, hz))
     NX, NY = ex.shape
     out = [np.empty((NX, NY), np.float64) for _ in range(6 if with_scale else 3)]

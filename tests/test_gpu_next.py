@@ -105,8 +105,9 @@ def test_fdtd2d_vs_oracle(ctx, NX, NY, T):
     hz0 = synth.uniform(444, (NX, NY), -1, 1)
     ex, ey, hz = ctx.fdtd2d(g(fict), g(ex0), g(ey0), g(hz0))
     refs, scales = o.fdtd2d(fict, ex0, ey0, hz0, with_scale=True)
-    # per element, against the summed magnitudes of the terms of its last update; FP32
-    # rounding grows with the steps (a step rounds at ~6e-8 of those magnitudes)
+    # per element, against the largest summed term magnitude in its domain of dependence
+    # (errors travel through later updates); FP32 rounding grows with the steps (a step
+    # rounds at ~6e-8 of those magnitudes)
     tol = 1e-6 * (1 + T)
     for got, ref, sc in zip((ex, ey, hz), refs, scales):
         assert o.max_err(h(got), ref, sc) <= tol

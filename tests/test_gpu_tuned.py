@@ -138,7 +138,7 @@ def check(inst, st, x):
         T = x["fict"].shape[0]
         refs, scales = o.fdtd2d(x["fict"], x["ex"], x["ey"], x["hz"], with_scale=True)
         err = max(o.max_err(h(st[key][0]), ref, sc) for key, ref, sc in zip(("ex", "ey", "hz"), refs, scales))
-        tol = 1e-6 * (1 + T)    # per element, against the magnitudes of its last update's terms
+        tol = 1e-6 * (1 + T)    # per element, against the term magnitudes of its domain of dependence
     else:
         raise AssertionError(f"no check for {inst.name}")
     return err, tol

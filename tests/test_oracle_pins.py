@@ -511,42 +511,73 @@ def test_fdtd_single_step_light_cone_pins_signs_and_offsets():
     assert np.count_nonzero(hz) == 5
 
 
-def test_fdtd_scales_light_cone_and_bound():
-    """Error scales of the FDTD oracle: after one step from a single hz impulse the scale
-    is non-zero exactly where an update read the impulse (0.5 on ey at (p, q) and (p+1, q),
-    on ex at (p, q) and (p, q+1); |hz| + c x the magnitudes around it on hz), and on random
-    fields it bounds |r| everywhere and the error of an FP32 evaluation element by element."""
+def _dependence_support(NX, NY, T, p, q):
+    """Cells whose final value can depend on hz[p][q] at the start, by boolean
+    propagation of the update rules' read sets (no arithmetic)."""
+    dx = np.zeros((NX, NY), bool)
+    dy = np.zeros((NX, NY), bool)
+    dh = np.zeros((NX, NY), bool)
+    dh[p, q] = True
+    for _ in range(T):
+        dy[0, :] = False                                   # row 0 is overwritten by the source
+        dy[1:, :] |= dh[1:, :] | dh[:-1, :]
+        dx[:, 1:] |= dh[:, 1:] | dh[:, :-1]
+        dh[:-1, :-1] |= dx[:-1, 1:] | dx[:-1, :-1] | dy[1:, :-1] | dy[:-1, :-1]
+    return dx, dy, dh
+
+
+def test_fdtd_scales_follow_the_domain_of_dependence_and_bound():
+    """Error scales of the FDTD oracle.  After one step from a single hz impulse (everything
+    else zero) an element's scale is the impulse's magnitude 1 wherever an update read it,
+    1 + 2c at the impulse (its own update's terms), 0 elsewhere; after several steps the
+    scales are non-zero exactly on the impulse's domain of influence, found by propagating
+    the update rules' read sets.  On random fields the scale bounds |r| everywhere and the
+    error of an FP32 evaluation (plain and with the H update fused) element by element."""
     NX, NY, p, q = 7, 8, 3, 4
     z = np.zeros((NX, NY), np.float32)
     hz0 = z.copy()
     hz0[p, q] = 1.0
     (ex, ey, hz), (sx, sy, sh) = o.fdtd2d(np.zeros(1, np.float32), z, z, hz0, with_scale=True)
     want = np.zeros((NX, NY))
-    want[p, q] = want[p + 1, q] = 0.5
+    want[p, q] = want[p + 1, q] = 1.0
     assert np.array_equal(sy, want)
     want = np.zeros((NX, NY))
-    want[p, q] = want[p, q + 1] = 0.5
+    want[p, q] = want[p, q + 1] = 1.0
     assert np.array_equal(sx, want)
-    # hz at (p, q) read ex (p, q), (p, q+1) and ey (p, q), (p+1, q), each 0.5 in magnitude
-    assert sh[p, q] == 1.0 + C07 * 2.0
-    assert sh[p - 1, q] == C07 * 0.5 and sh[p, q - 1] == C07 * 0.5
-    assert np.count_nonzero(sh) == 5
-    # random fields, several steps: |r| <= s, and a float32 evaluation stays within a few
-    # roundings per step of s (it would not if the scale dropped a term somewhere)
+    want = np.zeros((NX, NY))
+    want[p, q] = 1.0 + C07 * 2.0
+    want[p - 1, q] = want[p + 1, q] = want[p, q - 1] = want[p, q + 1] = 1.0
+    assert np.array_equal(sh, want)
+    # several steps on a larger grid: the scales' support is the domain of influence
+    NX, NY, p, q, T = 23, 19, 9, 7, 6
+    hz0 = np.zeros((NX, NY), np.float32)
+    hz0[p, q] = 1.0
+    z = np.zeros((NX, NY), np.float32)
+    vals, scales = o.fdtd2d(np.zeros(T, np.float32), z, z, hz0, with_scale=True)
+    for v, sc, dep in zip(vals, scales, _dependence_support(NX, NY, T, p, q)):
+        assert np.array_equal(sc > 0, dep)
+        assert not np.any(v[~dep])
+    # random fields, several steps: |r| <= s, and an FP32 evaluation stays within a few
+    # roundings per step of s
     T = 8
     fict, ex0, ey0, hz0 = _fdtd_inputs(31, 29, T, 341)
     refs, scales = o.fdtd2d(fict, ex0, ey0, hz0, with_scale=True)
     for r, sc in zip(refs, scales):
         assert np.all(np.abs(r) <= sc * (1 + 1e-15))
-    ex, ey, hz = (v.astype(np.float32).copy() for v in (ex0, ey0, hz0))
     half, c = np.float32(0.5), np.float32(0.7)
-    for t in range(T):
-        ey[0, :] = fict[t]
-        ey[1:, :] -= half * (hz[1:, :] - hz[:-1, :])
-        ex[:, 1:] -= half * (hz[:, 1:] - hz[:, :-1])
-        hz[:-1, :-1] -= c * (ex[:-1, 1:] - ex[:-1, :-1] + ey[1:, :-1] - ey[:-1, :-1])
-    errs = [o.max_err(g, r, sc) for g, r, sc in zip((ex, ey, hz), refs, scales)]
-    assert 0 < max(errs) <= 1e-6 * (1 + T), errs
+    for fused in (False, True):
+        ex, ey, hz = (v.astype(np.float32).copy() for v in (ex0, ey0, hz0))
+        for t in range(T):
+            ey[0, :] = fict[t]
+            ey[1:, :] -= half * (hz[1:, :] - hz[:-1, :])
+            ex[:, 1:] -= half * (hz[:, 1:] - hz[:, :-1])
+            s = ex[:-1, 1:] - ex[:-1, :-1] + ey[1:, :-1] - ey[:-1, :-1]
+            if fused:   # one rounding of hz - c*s (exact in FP64 for FP32 operands)
+                hz[:-1, :-1] = (hz[:-1, :-1].astype(np.float64) - np.float64(c) * s).astype(np.float32)
+            else:
+                hz[:-1, :-1] -= c * s
+        errs = [o.max_err(g, r, sc) for g, r, sc in zip((ex, ey, hz), refs, scales)]
+        assert 0 < max(errs) <= 1e-6 * (1 + T), errs
 
 
 def test_gemm_split3_drops_exactly_the_lo_lo_term():

@@ -144,58 +144,135 @@ def gpu_state():
             for card, vals in doc.items() if isinstance(vals, dict)}
 
 
-def cpu_baseline(budget_s=20.0):
-    """Time the FP64 oracle on a bounded sample of the batch: its instances in size order until
-    `budget_s` seconds of oracle work have been spent."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline():
+    """The FP64 oracle timed per kernel at the measured workloads' sizes, with all of the
+    host's threads and with one (operand generation outside the timing; median of 3 for
+    calls under 1 s).  Single-threaded, the chained product and the correlation run at
+    1024 instead of 2048 (about 20 s each otherwise); their rate is what is reported."""
     from oracle import oracle
-    from paper_1810_10496_amd import synth, workloads as W
+    from paper_1810_10496_amd import synth
 
-    def make_sample():
-        """The batch's instances in size order (operands generated lazily)."""
-        for n in W.SIZES:
-            def gemm(n=n):
-                A, B, C, a, b = synth.gemm_inputs(n, workload=W.WORKLOAD)
-                oracle.gemm(A, B, C, a, b)
-            yield f"gemm/{n}", gemm, 2.0 * n ** 3 + 3.0 * n * n
+    def k_gemm(n):
+        A, B, C, a, b = synth.gemm_inputs(n, workload=1)
+        return (lambda: oracle.gemm(A, B, C, a, b)), 2.0 * n ** 3 + 3.0 * n * n, 16.0 * n * n
 
-            def gemm3(n=n):
-                A, B, C, D, a, b = synth.gemm3_inputs(n, workload=W.WORKLOAD)
-                oracle.gemm3(A, B, C, D, a, b)
-            yield f"gemm3/{n}", gemm3, 4.0 * n ** 3 + 3.0 * n * n
+    def k_gemm3(n):
+        A, B, C, D, a, b = synth.gemm3_inputs(n, workload=3)
+        return (lambda: oracle.gemm3(A, B, C, D, a, b)), 4.0 * n ** 3 + 3.0 * n * n, 20.0 * n * n
 
-            def pair(n=n):
-                A, x, z = synth.gemv_inputs(n, workload=W.WORKLOAD)
-                oracle.gemv(A, x), oracle.gemv_t(A, z)
-            yield f"gemv_pair/{n}", pair, 4.0 * n * n
+    def k_pair(n):
+        A, x, z = synth.gemv_inputs(n, workload=2)
+        return (lambda: (oracle.gemv(A, x), oracle.gemv_t(A, z))), 4.0 * n * n, 4.0 * (n * n + 4 * n)
 
-            def conv(n=n):
-                grid, taps = synth.conv2d_inputs(n, workload=W.WORKLOAD)
-                oracle.conv2d(grid, taps)
-            yield f"conv2d/{n}", conv, 17.0 * (n - 2) ** 2
+    def k_conv2d(n):
+        g, taps = synth.conv2d_inputs(n, workload=2)
+        return (lambda: oracle.conv2d(g, taps)), 17.0 * (n - 2) ** 2, 8.0 * n * n
 
-            def corr(n=n):
-                X, eps = synth.corr_inputs(n, workload=W.WORKLOAD)
-                oracle.corr(X, eps)
-            yield f"corr/{n}", corr, 4.0 * n * n + n * (n + 1) * n
+    def k_conv3d(n):
+        v, taps = synth.conv3d_inputs(n, workload=5)
+        return (lambda: oracle.conv3d(v, taps)), 53.0 * (n - 2) ** 3, 8.0 * n ** 3
 
-    sample = make_sample()
-    done, flops, t_total = [], 0.0, 0.0
-    for name, fn, fl in sample:
-        if t_total > 0 and t_total + fl / (flops / t_total) > 1.5 * budget_s:
-            break   # the next instance alone would overrun the budget
+    def k_colstats(n):
+        X, eps = synth.corr_inputs(n, workload=4)
+        return (lambda: oracle.colstats(X, eps)), 4.0 * n * n, 4.0 * (n * n + 2 * n)
+
+    def k_corr(n):
+        X, eps = synth.corr_inputs(n, workload=4)
+        return (lambda: oracle.corr(X, eps)), 4.0 * n * n + n * (n + 1) * n, 4.0 * (2 * n * n + 2 * n)
+
+    plan = [("gemm", k_gemm, 512, 512), ("gemv_pair", k_pair, 4096, 4096), ("conv2d", k_conv2d, 4096, 4096),
+            ("gemm3", k_gemm3, 2048, 1024), ("colstats", k_colstats, 4096, 4096), ("corr", k_corr, 2048, 1024),
+            ("conv3d", k_conv3d, 256, 256)]
+
+    def timed(fn):
         t0 = time.perf_counter()
-        fn()   # includes generating the operands (small next to the oracle's work)
+        fn()
         dt = time.perf_counter() - t0
-        t_total += dt
-        flops += fl
-        done.append(name)
-        if t_total > budget_s:
-            break
-    return dict(value=flops / t_total / 1e9, unit="GFLOP/s (algorithmic, FP64 oracle)",
-                cores=oracle.num_threads(), kind="oracle",
-                sample=f"first {len(done)} instances of the batch in size order (stopped after {budget_s:.0f} s): "
-                + ",".join(done),
-                seconds=round(t_total, 3), gflop=round(flops / 1e9, 3))
+        if dt >= 1.0:
+            return dt
+        ts = [dt]
+        for _ in range(2):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return statistics.median(ts)
+
+    all_threads = oracle.num_threads()
+    rows, flops_all, secs_all = [], 0.0, 0.0
+    try:
+        for name, make, n_all, n_one in plan:
+            fn, fl, by = make(n_all)
+            oracle.set_threads(all_threads)
+            t_all = timed(fn)
+            if n_one != n_all:
+                fn, fl1, by1 = make(n_one)
+            else:
+                fl1, by1 = fl, by
+            oracle.set_threads(1)
+            t_one = timed(fn)
+            del fn
+            flops_all += fl
+            secs_all += t_all
+            rows.append(dict(kernel=name, size=n_all, all_threads_s=round(t_all, 4),
+                             all_threads_gflops=round(fl / t_all / 1e9, 2), all_threads_gbs=round(by / t_all / 1e9, 2),
+                             one_thread_size=n_one, one_thread_s=round(t_one, 4),
+                             one_thread_gflops=round(fl1 / t_one / 1e9, 3)))
+    finally:
+        oracle.set_threads(all_threads)
+    return dict(value=round(flops_all / secs_all / 1e9, 3), unit="GFLOP/s (algorithmic, FP64 oracle, all threads)",
+                cores=all_threads, kind="oracle", cpu=_cpu_model(),
+                sample="one call of each kernel at its workload size (gemm 512, matvec pair 4096^2, 2D stencil "
+                       "4096^2, chained product 2048, column statistics 4096^2, correlation 2048, 3D stencil "
+                       "256^3); one thread: chained product and correlation at 1024",
+                seconds=round(secs_all, 3), per_kernel=rows)
+
+
+# read-dominated operations are measured against the read ceiling, the stencils (one
+# read and one write of the grid) against the copy ceiling
+READ_OPS = ("gemv", "gemv_t", "gemv_pair", "colstats", "gesummv", "mvt")
+
+
+def ceiling_for(op, read_gbs, copy_gbs):
+    return ("read", read_gbs) if op in READ_OPS else ("copy", copy_gbs)
+
+
+def stream_ceilings(ctx, dev, stream, rounds=8):
+    """GB/s of the library's read and copy probes over four 512 MiB buffers in turn."""
+    import torch
+    n = (512 << 20) // 4
+    bufs = [torch.rand(n, device=dev) for _ in range(4)]
+    sums = torch.empty(ctx.STREAM_BLOCKS, device=dev)
+    dsts = [torch.empty(n, device=dev) for _ in range(2)]
+    torch.cuda.synchronize()
+    out = {}
+    for kind in ("read", "copy"):
+        def one(r):
+            if kind == "read":
+                ctx.stream_probe("read", bufs[r % 4], sums, stream=stream)
+            else:
+                ctx.stream_probe("copy", bufs[r % 4], dsts[r % 2], stream=stream)
+        for r in range(4):
+            one(r)
+        ctx.timer_start(stream)
+        for r in range(4 * rounds):
+            one(r)
+        ms = ctx.timer_stop(stream)
+        moved = n * 4 * (1 if kind == "read" else 2) * 4 * rounds
+        out[kind] = moved / (ms * 1e-3) / 1e9
+    del bufs, dsts
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -244,6 +321,18 @@ def main():
     sides = ["default", "tuned"] + (["k1", "k3"] if reuse else [])
     log(f"reuse assignments: {len(reuse)}")
 
+    def variant_kind(inst):
+        ents = [e for e in applied if e["family"] in inst.families
+                and int(e["bucket"]) == api.Context.size_bucket(inst.size) and e["vid"] >= 0
+                and not e.get("is_default")]
+        if not ents:
+            return "default kept"
+        from paper_1810_10496_amd import codegen
+        knobs = any(dict(e["knobs"]) != dict(codegen.FAMILIES[e["family"]].defaults) for e in ents)
+        pipe = any(e["pipeline"] != codegen.DEFAULT_PIPELINE or e.get("opt_flags")
+                   or list(e.get("llc_flags", ["-O3"])) != ["-O3"] for e in ents)
+        return {(True, False): "knobs only", (False, True): "pipeline only"}.get((knobs, pipe), "knobs and pipeline")
+
     def variant_for(fam, size, side):
         if side == "tuned":
             vid = chosen.get((fam, api.Context.size_bucket(size)))
@@ -286,23 +375,12 @@ def main():
     wall_ms = (time.perf_counter() - t0) * 1e3
     ms_per_step = ev_ms / args.steps
 
-    # ---- the box's practical HBM ceiling: a plain device copy (read + write) of 256 MiB
-    # buffers, rotating over four pairs so the Infinity Cache cannot serve it
-    nfl = (256 << 20) // 4
-    cbufs = [(torch.rand(nfl, device=dev), torch.empty(nfl, device=dev)) for _ in range(4)]
-    for src_, dst_ in cbufs:
-        dst_.copy_(src_)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for r in range(20):
-        cbufs[r % 4][1].copy_(cbufs[r % 4][0])
-    e1.record()
-    e1.synchronize()
-    copy_gbs = 2 * nfl * 4 * 20 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del cbufs
-    torch.cuda.empty_cache()
-    log(f"device copy ceiling: {copy_gbs:.0f} GB/s")
+    # ---- the chip's practical HBM ceilings, from the library's own probes: every element
+    # of a buffer read once, and a copy; 512 MiB buffers in turn (2 GiB read, 1 GiB copied
+    # per round), far beyond the 256 MB Infinity Cache
+    ceil = stream_ceilings(ctx, dev, stream)
+    read_gbs, copy_gbs = ceil["read"], ceil["copy"]
+    log(f"HBM ceilings: read {read_gbs:.0f} GB/s, copy {copy_gbs:.0f} GB/s")
 
     # ---- per-instance default vs tuned ----------------------------------------------------------
     rows = []
@@ -321,15 +399,27 @@ def main():
                          speedup=round(tdm / ttm, 4), achieved=round(ach / 1e9, 1), unit=unit,
                          frac=round(ach / peak, 4), gflops=round(inst.flops / (ttm * 1e-3) / 1e9, 1)))
         if inst.bound == "hbm":
-            rows[-1]["frac_of_copy"] = round(ach / 1e9 / copy_gbs, 4)
+            kind, cg = ceiling_for(inst.op, read_gbs, copy_gbs)
+            rows[-1]["frac_of_ceiling"] = round(ach / 1e9 / cg, 4)
+            rows[-1]["ceiling"] = kind
+        rows[-1]["variant"] = variant_kind(inst)
         for side in ("k1", "k3"):
             if side in med:
                 rows[-1][f"reuse_{side}_us"] = round(med[side] * 1e3, 2)
                 rows[-1][f"reuse_{side}_speedup"] = round(tdm / med[side], 4)
 
-    def gm(key):
-        return math.exp(sum(math.log(r[key]) for r in rows) / len(rows))
+    def gm(key, sel=None):
+        vals = [r[key] for r in rows if sel is None or sel(r)]
+        return round(math.exp(sum(math.log(v) for v in vals) / len(vals)), 4) if vals else None
     geo = gm("speedup")
+    by_size = {str(z): gm("speedup", lambda r, z=z: r["instance"].endswith(f"/{z}")) for z in sizes}
+    by_size[str(W.CONV3D_SIZE) + "^3"] = gm("speedup", lambda r: r["instance"].startswith("conv3d/"))
+    # where the tuned speedups come from: instances whose tuned variants differ from the
+    # default only in knobs (standard -O3 pipeline), those whose pipeline changed too, and
+    # those that kept the built-in default
+    split = {k: dict(instances=sum(1 for r in rows if r["variant"] == k), geomean=gm("speedup", lambda r, k=k:
+                                                                                      r["variant"] == k))
+             for k in ("knobs only", "pipeline only", "knobs and pipeline", "default kept")}
 
     # dominant kernel: pk_gemm at the largest GEMM instance, tuned variant
     big = max((r for r in rows if r["instance"].startswith("gemm/")), key=lambda r: int(r["instance"].split("/")[1]))
@@ -363,8 +453,12 @@ def main():
                 row.update(default_us=round(td * 1e3, 2), speedup=round(td / t, 4))
             if inst.bound == "hbm":
                 gbs = inst.bytes / (t * 1e-3) / 1e9
+                kind, cg = ceiling_for(inst.op, read_gbs, copy_gbs)
                 row.update(gbs=round(gbs, 1), peak_gbs=PEAK_HBM / 1e9, frac=round(gbs * 1e9 / PEAK_HBM, 4),
-                           frac_of_copy=round(gbs / copy_gbs, 4))
+                           frac_of_ceiling=round(gbs / cg, 4), ceiling=kind)
+            elif inst.bound == "infinity_cache":
+                # the operands stay in the 256 MB Infinity Cache across the call: no HBM figure
+                row.update(gbs=round(inst.bytes / (t * 1e-3) / 1e9, 1), bound="infinity_cache")
             else:
                 tf = inst.flops / (t * 1e-3) / 1e12
                 fam = inst.families[-1]
@@ -375,6 +469,33 @@ def main():
                     row["mfma_frac"] = round(3 * tf / peak, 4)    # three bf16 products per useful one
             out_rows.append(row)
         return out_rows
+
+    # ---- the phase-order exploration's best orders (default knobs, random pass orders,
+    # minimised) against the default pipeline, each at its family's benchmark size
+    order_rows = []
+    if not args.sizes:
+        for fam, (vid, e) in sorted(tuned.load_orders(ctx).items()):
+            for inst in W.family_instances(fam, (e["size"],)):
+                copies = max(1, min(args.reps, math.ceil(ROTATE_BYTES / max(inst.footprint, 1))))
+                inst.state = inst.make(dev, copies)
+                inst.state["_copies"] = copies
+                ts = {"default": [], "order": []}
+                for _ in range(args.repeats):
+                    for side, v in (("default", ctx.variant_default(fam)), ("order", vid)):
+                        ctx.variant_select(fam, v)
+                        try:
+                            ts[side].append(per_launch_ms(ctx, stream, lambda i: inst.run(
+                                ctx, inst.state, i % inst.state["_copies"], stream), args.reps, 1))
+                        finally:
+                            ctx.variant_select(fam, -1)
+                td, to = statistics.median(ts["default"]), statistics.median(ts["order"])
+                order_rows.append(dict(family=fam, instance=inst.name, default_us=round(td * 1e3, 2),
+                                       order_us=round(to * 1e3, 2), speedup=round(td / to, 4),
+                                       passes=len(e["pipeline"].split(","))))
+                inst.state = None
+                torch.cuda.empty_cache()
+        if order_rows:
+            log(f"phase orders: {len(order_rows)} families timed")
 
     prec_rows, next_rows = [], []
     if not args.sizes:
@@ -402,9 +523,14 @@ def main():
                                "colstats, corr at N in " + ",".join(map(str, sizes)) + "; conv3d 256^3",
                    "instances": len(insts), "tuned_entries": len(chosen), "reps_per_timing_graph": args.reps},
         "roofline": roof,
-        "hbm_copy_ceiling_gbs": round(copy_gbs, 1),
+        "hbm_ceilings_gbs": {k: round(v, 1) for k, v in ceil.items()},
+        "geomean_by_size": by_size,
+        "speedup_sources": split,
         "reuse": ({"cosine_k1": round(gm("reuse_k1_speedup"), 4), "cosine_k3": round(gm("reuse_k3_speedup"), 4),
                    "tuner_estimates": tuned.reuse_summary(args.table or tuned.TABLE)} if reuse else None),
+        "phase_orders": ({"geomean": round(math.exp(sum(math.log(r["speedup"]) for r in order_rows)
+                                                   / len(order_rows)), 4), "rows": order_rows}
+                         if order_rows else None),
         "instances": rows,
         "precisions": prec_rows,
         "next_rows": next_rows,

@@ -111,7 +111,8 @@ typedef enum pk_family {
     PK_FAMILY_FDTD = 15,
     PK_FAMILY_GEMM_BF16_WS = 16,   /* bf16 GEMM from prepared operands (pk_sgemm_ws) */
     PK_FAMILY_GEMM_SPLIT_WS = 17,  /* split-bf16 GEMM from prepared operands (pk_sgemm_ws) */
-    PK_FAMILY_COUNT = 18
+    PK_FAMILY_STREAM = 18,         /* bandwidth probes (pk_stream_probe) */
+    PK_FAMILY_COUNT = 19
 } pk_family;
 
 typedef struct pk_context pk_context;
@@ -319,6 +320,15 @@ pk_status pk_graph_time(pk_context *ctx, pk_graph *g, int reps, pk_stream stream
 /* Evict caches (L2 and the Infinity Cache) by writing a 512 MiB scratch
  * buffer owned by the context (allocated on first use). */
 pk_status pk_cache_flush(pk_context *ctx, pk_stream stream);
+/* Bandwidth probes, the ceilings the memory-bound kernels are reported against
+ * (not one of the paper's kernels).  kind 0 (read): every one of the n floats
+ * of src is read once with 16-byte loads and dst[b] receives the sum of what
+ * block b read, for b < PK_STREAM_BLOCKS (dst must hold that many floats);
+ * kind 1 (copy): dst[i] = src[i] for i < n (src and dst must not overlap).
+ * src and dst must be 16-byte aligned (else PK_ERR_ALIGNMENT); n >= 0. */
+#define PK_STREAM_BLOCKS 2048
+pk_status pk_stream_probe(pk_context *ctx, int kind, const float *src, float *dst, int64_t n,
+                          pk_stream stream);
 
 #ifdef __cplusplus
 }

@@ -38,6 +38,18 @@ int oracle_num_threads(void)
 #endif
 }
 
+/* Threads of the parallel loops that follow (n >= 1); the results do not depend
+ * on it (every sum runs in a fixed order inside one thread). */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------
  * Dense product (GEMM, Sec. 2.2):  r_ij = alpha * sum_k a_ik b_kj + beta * c_ij
  * A is M x K (row stride lda), B is K x N (ldb), C is M x N (ldc).

@@ -49,6 +49,7 @@ def _load():
         build(force=True)
     lib = ctypes.CDLL(_LIB_PATH)
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
     lib.oracle_gemm.argtypes = [_i64, _i64, _i64, _f32, _f32p, _i64, _f32p, _i64, _f32,
                                 _f32p, _i64, _f64p]
     lib.oracle_gemm3.argtypes = [_i64, _i64, _i64, _i64, _f32, _f32p, _i64, _f32p, _i64,
@@ -82,6 +83,14 @@ def _c32(a):
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's parallel loops from now on; returns the previous count."""
+    lib = _load()
+    prev = int(lib.oracle_num_threads())
+    lib.oracle_set_threads(int(n))
+    return prev
 
 
 def gemm(A, B, C, alpha, beta):

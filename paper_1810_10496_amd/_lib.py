@@ -63,6 +63,7 @@ SIGNATURES = [
     ("pk_timer_stop", c_st, [c_vp, c_vp, ctypes.POINTER(ctypes.c_double)]),
     ("pk_graph_time", c_st, [c_vp, c_vp, ctypes.c_int, c_vp, ctypes.POINTER(ctypes.c_double)]),
     ("pk_cache_flush", c_st, [c_vp, c_vp]),
+    ("pk_stream_probe", c_st, [c_vp, ctypes.c_int, c_vp, c_vp, c_i64, c_vp]),
 ]
 
 _lib = None

@@ -418,6 +418,14 @@ class Context:
     def cache_flush(self, stream=None):
         _check(self._lib.pk_cache_flush(self.handle, _stream(stream)))
 
+    STREAM_BLOCKS = 2048     # PK_STREAM_BLOCKS
+
+    def stream_probe(self, kind, src, dst, stream=None):
+        """pk_stream_probe: kind "read" (dst: STREAM_BLOCKS block sums) or "copy"."""
+        _check(self._lib.pk_stream_probe(self.handle, {"read": 0, "copy": 1}[kind], _ptr(src), _ptr(dst),
+                                         src.numel(), _stream(stream)))
+        return dst
+
 
 class Graph:
     def __init__(self, ctx: Context):

@@ -22,6 +22,7 @@ import os
 import shutil
 import subprocess
 import tempfile
+import threading
 from dataclasses import dataclass, field
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -88,6 +89,7 @@ FAMILIES = {f.name: f for f in [
     _fs("gemm_split_ws", 17, "gemm_bf.hip", {"PREC": 2},
         dict(BM=256, BN=256, BK=32, WAVES_M=4, WAVES_N=4, ORDER=3, LDS_PAD=8, PIPE=1, DSTAGES=2, SCHED=0),
         "gemm", "split"),
+    _fs("stream", 18, "stream.hip", {}, dict(NTHREADS=256, UNROLL=4), "stream"),
 ]}
 FAMILY_BY_ID = {f.fid: f for f in FAMILIES.values()}
 
@@ -150,6 +152,35 @@ def emit_ir(spec: FamilySpec, knobs: dict, out_bc: str, timeout: float = 120.0) 
     _run("frontend", cmd, timeout, cwd=KDIR)
 
 
+_FRONTEND = {}                  # (family, knobs) -> un-optimised device IR (bitcode bytes)
+_FRONTEND_LOCK = threading.Lock()
+
+
+def frontend_ir(family: str, knobs: dict | None = None, timeout: float = 120.0) -> bytes:
+    """The front end's output for one knob setting, computed once per process: the IR
+    depends only on the source, the family's fixed macros and the knobs, so variants
+    that differ only in their pipeline (a phase-order exploration) share it."""
+    spec = FAMILIES[family]
+    key = (family, tuple(sorted(macro_flags(spec, knobs or {}))))
+    with _FRONTEND_LOCK:
+        hit = _FRONTEND.get(key)
+    if hit is not None:
+        return hit
+    wd = tempfile.mkdtemp(prefix="pkfe_")
+    try:
+        bc = os.path.join(wd, "in.bc")
+        emit_ir(spec, knobs or {}, bc, timeout)
+        with open(bc, "rb") as f:
+            code = f.read()
+    finally:
+        shutil.rmtree(wd, ignore_errors=True)
+    with _FRONTEND_LOCK:
+        if len(_FRONTEND) > 256:
+            _FRONTEND.clear()
+        _FRONTEND[key] = code
+    return code
+
+
 def compile_variant(family: str, knobs: dict | None = None, pipeline: str = DEFAULT_PIPELINE,
                     llc_flags: tuple = ("-O3",), workdir: str | None = None,
                     timeout: float = 120.0, keep_ir: bool = False, opt_flags: tuple = ()) -> Built:
@@ -167,7 +198,8 @@ def compile_variant(family: str, knobs: dict | None = None, pipeline: str = DEFA
         obj = os.path.join(wd, "out.o")
         co = os.path.join(wd, "out.co")
         t0 = time.time()
-        emit_ir(spec, knobs, bc, timeout)
+        with open(bc, "wb") as f:
+            f.write(frontend_ir(family, knobs, timeout))
         t["frontend"] = time.time() - t0
         t0 = time.time()
         _run("opt", [tool("opt"), "-mtriple=amdgcn-amd-amdhsa", f"-mcpu={ARCH}", *opt_flags,

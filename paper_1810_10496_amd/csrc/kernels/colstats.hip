@@ -9,7 +9,7 @@
 // so the segment is read from memory once: a Neumaier-compensated sum gives
 // the segment mean, then the squared deviations about that mean are summed
 // from the same registers.  Per segment it writes (sum_hi, sum_lo, M2).
-// Stage 2 (pk_colstats_merge): per column, segments are folded in ascending
+// Stage 2 (pk_colstats_merge): per column, segments are folded in a fixed
 // order: the total sum by Neumaier summation of every (hi, lo) term, the mean
 // from it, and M2 = sum_b [M2_b + n_b (mu_b - mu)^2] (all terms >= 0, so the
 // large column offsets never cancel).
@@ -32,7 +32,11 @@ constexpr int NT = 64 * WAVES;
 constexpr int RPW = (ROWS + WAVES - 1) / WAVES;
 constexpr int STRIP = 64 * VEC;
 
-PK_DEFINE_KNOBS(PKF_COLSTATS, ROWS, STRIP, ROWS, WAVES, 1, VEC, 1, 1, ORDER, 0, 0, NT,
+// wavefronts per block of the merge (pk_colstats_merge); recorded in knob X2, which
+// the runtime launches it with
+constexpr int MW = 8;
+
+PK_DEFINE_KNOBS(PKF_COLSTATS, ROWS, STRIP, ROWS, WAVES, 1, VEC, 1, 1, ORDER, 0, MW, NT,
                 3 * WAVES * STRIP * 4, PK_KERNEL_ABI_VERSION, 0)
 
 template <int V>
@@ -163,63 +167,95 @@ extern "C" __global__ void __launch_bounds__(NT) pk_colstats_partial(pk_colstats
         partial_body<1>(a, red, smean);
 }
 
-// 256 threads = 16 columns x 16 sub-lanes.  Sub-lane u folds the segments
-// b = u, u+16, ... in ascending order; the 16 partial results of a column are
-// then combined in a fixed order, so the result does not depend on timing.
-constexpr int MCOLS = 16, MSUB = 16;
-extern "C" __global__ void __launch_bounds__(256) pk_colstats_merge(pk_colstats_args a) {
-    const int cl = threadIdx.x % MCOLS;
-    const int u = threadIdx.x / MCOLS;
-    __shared__ float sh[2][MSUB][MCOLS];
-    __shared__ float smu[MCOLS];
-    for (int64_t c0 = (int64_t)blockIdx.x * MCOLS; c0 < a.m; c0 += (int64_t)gridDim.x * MCOLS) {
-        const int64_t j = c0 + cl;
+// The merge: a block is MW wavefronts over 64 columns (lane = column).  Wavefront w
+// takes the segments b = w, w+MW, ... in ascending order; it loads the (hi, lo, M2)
+// of up to MQ of them at once into registers and folds them from there, so both
+// passes of a batch wait for memory once (and the second pass reads nothing when
+// a wavefront has at most MQ segments).  The MW results of a column are combined
+// in the order w = 0..MW-1, so the result does not depend on timing.
+constexpr int MQ = 16;
+extern "C" __global__ void __launch_bounds__(64 * MW) pk_colstats_merge(pk_colstats_args a) {
+    if (blockDim.x != 64 * MW)
+        return;
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    __shared__ float sh[2][MW][64];
+    __shared__ float smu[64];
+    const bool one_batch = a.segments <= MW * MQ;
+    for (int64_t c0 = (int64_t)blockIdx.x * 64; c0 < a.m; c0 += (int64_t)gridDim.x * 64) {
+        const int64_t j = c0 + lane;
         const bool valid = j < a.m;
+        float hv[MQ], lv[MQ], mv[MQ];
         float hi = 0.f, lo = 0.f;
         if (valid) {
-#pragma unroll 4
-            for (int b = u; b < a.segments; b += MSUB) {
-                const float *p = a.part + (int64_t)b * 3 * a.m;
-                pk_neumaier(hi, lo, p[j]);
-                pk_neumaier(hi, lo, p[a.m + j]);
+            for (int b0 = w; b0 < a.segments; b0 += MQ * MW) {
+#pragma unroll
+                for (int q = 0; q < MQ; ++q) {
+                    const int b = b0 + q * MW;
+                    const float *p = a.part + (int64_t)min(b, a.segments - 1) * 3 * a.m;
+                    hv[q] = p[j];
+                    lv[q] = p[a.m + j];
+                    mv[q] = p[2 * a.m + j];
+                }
+#pragma unroll
+                for (int q = 0; q < MQ; ++q) {
+                    if (b0 + q * MW < a.segments) {
+                        pk_neumaier(hi, lo, hv[q]);
+                        pk_neumaier(hi, lo, lv[q]);
+                    }
+                }
             }
         }
-        sh[0][u][cl] = hi;
-        sh[1][u][cl] = lo;
+        sh[0][w][lane] = hi;
+        sh[1][w][lane] = lo;
         __syncthreads();
-        if (u == 0) {
+        if (w == 0) {
             float th = 0.f, tl = 0.f;
 #pragma unroll
-            for (int q = 0; q < MSUB; ++q) {
-                pk_neumaier(th, tl, sh[0][q][cl]);
-                pk_neumaier(th, tl, sh[1][q][cl]);
+            for (int q = 0; q < MW; ++q) {
+                pk_neumaier(th, tl, sh[0][q][lane]);
+                pk_neumaier(th, tl, sh[1][q][lane]);
             }
-            smu[cl] = (th + tl) / (float)a.n;
+            smu[lane] = (th + tl) / (float)a.n;
         }
         __syncthreads();
-        const float mu = smu[cl];
+        const float mu = smu[lane];
         float m2 = 0.f, m2c = 0.f;
         if (valid) {
-#pragma unroll 4
-            for (int b = u; b < a.segments; b += MSUB) {
-                const float *p = a.part + (int64_t)b * 3 * a.m;
-                const int64_t r0 = (int64_t)b * a.seg_rows;
-                const float nb = (float)(min(r0 + (int64_t)a.seg_rows, a.n) - r0);
-                const float d = (p[j] + p[a.m + j]) / nb - mu;
-                pk_neumaier(m2, m2c, p[2 * a.m + j]);
-                pk_neumaier(m2, m2c, nb * d * d);
+            for (int b0 = w; b0 < a.segments; b0 += MQ * MW) {
+                if (!one_batch) {
+#pragma unroll
+                    for (int q = 0; q < MQ; ++q) {
+                        const int b = b0 + q * MW;
+                        const float *p = a.part + (int64_t)min(b, a.segments - 1) * 3 * a.m;
+                        hv[q] = p[j];
+                        lv[q] = p[a.m + j];
+                        mv[q] = p[2 * a.m + j];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < MQ; ++q) {
+                    const int b = b0 + q * MW;
+                    if (b < a.segments) {
+                        const int64_t r0 = (int64_t)b * a.seg_rows;
+                        const float nb = (float)(min(r0 + (int64_t)a.seg_rows, a.n) - r0);
+                        const float d = (hv[q] + lv[q]) / nb - mu;
+                        pk_neumaier(m2, m2c, mv[q]);
+                        pk_neumaier(m2, m2c, nb * d * d);
+                    }
+                }
             }
         }
         __syncthreads();
-        sh[0][u][cl] = m2;
-        sh[1][u][cl] = m2c;
+        sh[0][w][lane] = m2;
+        sh[1][w][lane] = m2c;
         __syncthreads();
-        if (u == 0 && valid) {
+        if (w == 0 && valid) {
             float M = 0.f, Mc = 0.f;
 #pragma unroll
-            for (int q = 0; q < MSUB; ++q) {
-                pk_neumaier(M, Mc, sh[0][q][cl]);
-                pk_neumaier(M, Mc, sh[1][q][cl]);
+            for (int q = 0; q < MW; ++q) {
+                pk_neumaier(M, Mc, sh[0][q][lane]);
+                pk_neumaier(M, Mc, sh[1][q][lane]);
             }
             const float sd = sqrtf((M + Mc) / (float)(a.n - 1));
             a.mean[j] = mu;

@@ -45,10 +45,14 @@ constexpr int XMAX = 4096;   // x staged in LDS when N <= XMAX
 #define FAMILY PKF_GEMV_PAIR
 #endif
 
+// wavefronts per block of the partial-sum reduce (kinds 1/2, pk_colsum_reduce)
+constexpr int RW = 8;
+
 // TM: rows per wavefront (kind 0) or per block (kinds 1/2); TN: columns per
-// block (kinds 1/2); X1: columns per wavefront (rows of the pair's part1 = N / X1)
+// block (kinds 1/2); X1: columns per wavefront (rows of the pair's part1 = N / X1);
+// X2: the reduce's wavefronts per block (kinds 1/2), which the runtime launches with
 PK_DEFINE_KNOBS(FAMILY, ROWS, (GEMV_KIND) == 0 ? 64 * VEC : WAVES * 64 * VEC, 0, WAVES, 1, VEC, UNROLL,
-                USE_LDS, ORDER, 64 * VEC, 0, NT, 0, PK_KERNEL_ABI_VERSION, 0)
+                USE_LDS, ORDER, 64 * VEC, (GEMV_KIND) == 0 ? 0 : RW, NT, 0, PK_KERNEL_ABI_VERSION, 0)
 
 #if GEMV_KIND == 0
 // ---------------------------------------------------------------- y = A x --
@@ -277,40 +281,53 @@ extern "C" __global__ void __launch_bounds__(NT) pk_gemv_pair_partial(pk_gemvt_a
         colblock_body<1>(a);
 }
 
-// y[j] = sum_r P[r][j].  256 threads = 16 columns x 16 sub-lanes; sub-lane u
-// adds rows r = u, u+16, ... in ascending order and the 16 partial sums of a
-// column are added in a fixed order (bitwise reproducible).  Blocks
-// [0, ceil(n1/16)) handle P1, the rest P2 (when present).
-constexpr int RCOLS = 16, RSUB = 16;
-extern "C" __global__ void __launch_bounds__(256) pk_colsum_reduce(pk_reduce_args a) {
-    const int cl = threadIdx.x % RCOLS;
-    const int u = threadIdx.x / RCOLS;
-    const int64_t b1 = (a.n1 + RCOLS - 1) / RCOLS;
+// y[j] = sum_r P[r][j].  A block is RW wavefronts over 64 columns (lane = column):
+// wavefront w adds the rows r = w, w+RW, ... in ascending order, issuing a batch of
+// RB rows' loads before the first add of the batch (the partials were just written
+// and sit in the L2 or the Infinity Cache, so what costs is the wait, not the
+// bytes), and the RW wavefront sums of a column are added in the order w = 0..RW-1:
+// the result does not depend on timing.  Blocks [0, ceil(n1/64)) handle P1, the
+// rest P2 (when present).
+constexpr int RB = 16;
+extern "C" __global__ void __launch_bounds__(64 * RW) pk_colsum_reduce(pk_reduce_args a) {
+    if (blockDim.x != 64 * RW)
+        return;
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int64_t b1 = (a.n1 + 63) / 64;
     const float *P;
     float *y;
     int64_t n, j;
     int rows;
     if ((int64_t)blockIdx.x < b1) {
         P = a.P1; y = a.y1; n = a.n1; rows = a.rows1;
-        j = (int64_t)blockIdx.x * RCOLS + cl;
+        j = (int64_t)blockIdx.x * 64 + lane;
     } else {
         P = a.P2; y = a.y2; n = a.n2; rows = a.rows2;
-        j = ((int64_t)blockIdx.x - b1) * RCOLS + cl;
+        j = ((int64_t)blockIdx.x - b1) * 64 + lane;
     }
-    __shared__ float sh[RSUB][RCOLS];
+    __shared__ float sh[RW][64];
     float s = 0.f;
     if (y != nullptr && j < n) {
-#pragma unroll 4
-        for (int r = u; r < rows; r += RSUB)   // rows == 0 leaves zeros (empty sums)
-            s += P[(int64_t)r * n + j];
-    }
-    sh[u][cl] = s;
-    __syncthreads();
-    if (u == 0 && y != nullptr && j < n) {
-        float t = 0.f;
+        for (int r0 = w; r0 < rows; r0 += RB * RW) {      // rows == 0 leaves zeros (empty sums)
+            float v[RB];
 #pragma unroll
-        for (int q = 0; q < RSUB; ++q)
-            t += sh[q][cl];
+            for (int q = 0; q < RB; ++q) {
+                const int r = r0 + q * RW;
+                v[q] = r < rows ? P[(int64_t)r * n + j] : 0.f;
+            }
+#pragma unroll
+            for (int q = 0; q < RB; ++q)
+                s += v[q];
+        }
+    }
+    sh[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && y != nullptr && j < n) {
+        float t = sh[0][lane];
+#pragma unroll
+        for (int q = 1; q < RW; ++q)
+            t += sh[q][lane];
         y[j] = t;
     }
 }

@@ -55,7 +55,8 @@ enum pk_family_id {
     PKF_FDTD = 15,       // FDTD-2D field updates
     PKF_GEMM_BF16_WS = 16,   // bf16 GEMM from operands prepared in a workspace (+ the preparation)
     PKF_GEMM_SPLIT_WS = 17,  // split-bf16 GEMM from prepared operands (+ the preparation)
-    PKF_COUNT = 18
+    PKF_STREAM = 18,         // bandwidth probes (read-only and copy ceilings)
+    PKF_COUNT = 19
 };
 
 // C <- alpha * A B + beta * C   (row-major, FP32 storage)
@@ -109,6 +110,13 @@ struct pk_reduce_args {
     int64_t n2;
     int32_t rows2;
     int32_t pad2_;
+};
+
+// bandwidth probes: read n floats of src (dst: one float per block) or copy them to dst
+struct pk_stream_args {
+    const float *src;
+    float *dst;
+    int64_t n;
 };
 
 // 3x3 stencil

@@ -100,12 +100,16 @@ const char *const kFnNames[PKF_COUNT][2] = {
     {"pk_fdtd_e", "pk_fdtd_h"},                        // FDTD
     {"pk_gemm_bf", "pk_gemm_prep"},                    // GEMM_BF16_WS
     {"pk_gemm_bf", "pk_gemm_prep"},                    // GEMM_SPLIT_WS
+    {"pk_stream_read", "pk_stream_copy"},              // STREAM
 };
 
 // smallest row-block / segment a gemv_t, gemv_pair or colstats variant may use
 // and the narrowest column strip; workspace bounds follow from these
 constexpr int kMinRowBlock = 16;
 constexpr int kMinStrip = 64;
+// the fixed-order reduce of the transposed matvec's partials and the column
+// statistics' merge: blocks of 8 wavefronts over 64 columns
+constexpr int kReduceThreads = 512;
 
 struct Variant {
     int family = -1;
@@ -177,10 +181,10 @@ pk_status load_module(pk_context *ctx, const void *code, size_t bytes, bool buil
             break;
         case PKF_GEMV_T: case PKF_GEMV_PAIR:
             ok = k[PK_K_TM] >= kMinRowBlock && k[PK_K_TN] >= kMinStrip && k[PK_K_X1] >= kMinStrip &&
-                 k[PK_K_TN] % k[PK_K_X1] == 0;
+                 k[PK_K_TN] % k[PK_K_X1] == 0 && k[PK_K_X2] * 64 == kReduceThreads;
             break;
         case PKF_COLSTATS:
-            ok = k[PK_K_TM] >= kMinRowBlock && k[PK_K_TN] >= kMinStrip;
+            ok = k[PK_K_TM] >= kMinRowBlock && k[PK_K_TN] >= kMinStrip && k[PK_K_X2] * 64 == kReduceThreads;
             break;
         case PKF_CONV2D: case PKF_CONV3D:
             ok = k[PK_K_TM] >= 1 && k[PK_K_TN] >= 1 && k[PK_K_TK] >= 1;
@@ -465,7 +469,7 @@ pk_status run_colstats(pk_context *ctx, int64_t n, int64_t m, const float *X, in
     a.segments = (int32_t)segs; a.seg_rows = rows;
     a.aligned = aligned16(X) && ldx % 4 == 0;
     PK_TRY(launch(v, 0, segs * strips, v->knobs[PK_K_THREADS], &a, sizeof a, s));
-    return launch(v, 1, std::min<int64_t>(cdiv(m, 16), 65535), 256, &a, sizeof a, s);
+    return launch(v, 1, std::min<int64_t>(cdiv(m, 64), 65535), kReduceThreads, &a, sizeof a, s);
 }
 
 }  // namespace
@@ -778,7 +782,7 @@ static pk_status gemvt_common(pk_context *ctx, bool pair, int64_t M, int64_t N, 
         pk_reduce_args r{};
         r.P1 = nullptr; r.y1 = y2; r.n1 = N; r.rows1 = 0;
         r.P2 = nullptr; r.y2 = pair ? y1 : nullptr; r.n2 = pair ? M : 0; r.rows2 = 0;
-        return launch(v, 1, cdiv(r.n1, 16) + cdiv(r.n2, 16), 256, &r, sizeof r, s);
+        return launch(v, 1, cdiv(r.n1, 64) + cdiv(r.n2, 64), kReduceThreads, &r, sizeof r, s);
     }
     if (rb > 0x7fffffff || strips > 0x7fffffff)
         return fail(PK_ERR_SHAPE, "problem too large");
@@ -796,7 +800,7 @@ static pk_status gemvt_common(pk_context *ctx, bool pair, int64_t M, int64_t N, 
     if (pair) {
         r.P2 = a.part1; r.y2 = y1; r.n2 = M; r.rows2 = (int32_t)wstrips;
     }
-    return launch(v, 1, cdiv(r.n1, 16) + (pair ? cdiv(r.n2, 16) : 0), 256, &r, sizeof r, s);
+    return launch(v, 1, cdiv(r.n1, 64) + (pair ? cdiv(r.n2, 64) : 0), kReduceThreads, &r, sizeof r, s);
 }
 
 pk_status pk_sgemv_t(pk_context *ctx, int64_t M, int64_t N, const float *A, int64_t lda, const float *z,
@@ -1364,6 +1368,25 @@ pk_status pk_cache_flush(pk_context *ctx, pk_stream stream) {
         int32_t pad;
     } a{(float *)ctx->flush_buf, (int64_t)(ctx->flush_bytes / 4), 0.f, 0};
     return launch(v, 1, 4096, 256, &a, sizeof a, (hipStream_t)stream);
+    PK_GUARD_END
+}
+
+pk_status pk_stream_probe(pk_context *ctx, int kind, const float *src, float *dst, int64_t n,
+                          pk_stream stream) {
+    PK_GUARD_BEGIN
+    g_err.clear();
+    PK_TRY(check_ctx(ctx));
+    if (kind != 0 && kind != 1)
+        return fail(PK_ERR_INVALID_ARG, "bad probe kind %d", kind);
+    if (n < 0)
+        return fail(PK_ERR_SHAPE, "negative size");
+    if (!aligned16(src) || !aligned16(dst))
+        return fail(PK_ERR_ALIGNMENT, "probe buffers must be 16-byte aligned");
+    PK_TRY(check_ptr(ctx, src, (size_t)n * 4, "src"));
+    PK_TRY(check_ptr(ctx, dst, kind == 0 ? (size_t)PK_STREAM_BLOCKS * 4 : (size_t)n * 4, "dst"));
+    const Variant *v = get_variant(ctx, ctx->def[PKF_STREAM]);
+    pk_stream_args a{src, dst, n};
+    return launch(v, kind, PK_STREAM_BLOCKS, v->knobs[PK_K_THREADS], &a, sizeof a, (hipStream_t)stream);
     PK_GUARD_END
 }
 

@@ -39,6 +39,25 @@ def read_reuse(path: str = TABLE) -> list[dict]:
     return list(doc.get("reuse", []))
 
 
+ORDERS = os.path.join(HERE, "tuned", "orders.json")
+
+
+def read_orders(path: str = ORDERS) -> list[dict]:
+    """The phase-order exploration's minimal best order per family (fixed default knobs),
+    as entries like the table's (family, size, knobs, pipeline, code_sha256)."""
+    if not os.path.exists(path):
+        return []
+    with open(path) as f:
+        doc = json.load(f)
+    out = []
+    for fam, e in sorted(doc.get("families", {}).items()):
+        if e.get("order") and e.get("code_sha256"):
+            out.append(dict(family=fam, size=int(e["size"]), knobs=dict(codegen.FAMILIES[fam].defaults),
+                            pipeline=",".join(e["order"]), llc_flags=["-O3"], opt_flags=[],
+                            code_sha256=e["code_sha256"]))
+    return out
+
+
 def reuse_summary(path: str = TABLE) -> dict:
     """The tuner's own estimates (cosine K=1/3, random-K control) stored with the table."""
     if not os.path.exists(path):
@@ -70,12 +89,35 @@ def code_for(entry: dict, build_missing: bool = True) -> bytes | None:
     return b.code
 
 
+def rebuild(entry: dict) -> bytes | None:
+    """Compile an entry from its description now; the cache keeps the result only if it
+    reproduces the recorded code object (a changed kernel source or tool chain makes
+    the entry stale, and a stale cached copy is removed, never loaded)."""
+    p = _cache_path(entry)
+    try:
+        b = codegen.compile_variant(entry["family"], entry.get("knobs", {}),
+                                    entry.get("pipeline", codegen.DEFAULT_PIPELINE),
+                                    tuple(entry.get("llc_flags", ["-O3"])),
+                                    opt_flags=tuple(entry.get("opt_flags", [])))
+    except codegen.CompileError:
+        b = None
+    if b is None or b.code_hash != entry["code_sha256"]:
+        if os.path.exists(p):
+            os.unlink(p)
+        return None
+    os.makedirs(CACHE, exist_ok=True)
+    with open(p, "wb") as f:
+        f.write(b.code)
+    return b.code
+
+
 def build_all(path: str = TABLE, jobs: int = 8) -> dict:
-    """Compile every entry of the table into the cache; returns {sha: ok}."""
-    entries = [e for e in read_table(path) + read_reuse(path) if not e.get("is_default")]
+    """Rebuild every entry of the table from source into the cache; returns {sha: ok}."""
+    entries = [e for e in read_table(path) + read_reuse(path) if not e.get("is_default")] + read_orders()
+    uniq = list({e["code_sha256"]: e for e in entries}.values())
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        res = list(ex.map(lambda e: code_for(e) is not None, entries))
-    return {e["code_sha256"]: ok for e, ok in zip(entries, res)}
+        res = list(ex.map(lambda e: rebuild(e) is not None, uniq))
+    return {e["code_sha256"]: ok for e, ok in zip(uniq, res)}
 
 
 def apply(ctx, path: str = TABLE, build_missing: bool = True) -> list[dict]:
@@ -95,6 +137,16 @@ def apply(ctx, path: str = TABLE, build_missing: bool = True) -> list[dict]:
         vid = ctx.variant_load(code)
         ctx.variant_set_best(e["family"], int(e["bucket"]), vid)
         out.append(dict(e, vid=vid))
+    return out
+
+
+def load_orders(ctx, path: str = ORDERS, build_missing: bool = True) -> dict:
+    """Load each family's best phase order (not registered as best); {family: variant id}."""
+    out = {}
+    for e in read_orders(path):
+        code = code_for(e, build_missing)
+        if code is not None:
+            out[e["family"]] = (ctx.variant_load(code), e)
     return out
 
 

@@ -8,6 +8,7 @@
     python -m paper_1810_10496_amd.tuner table       --workdir D [--out path]
     python -m paper_1810_10496_amd.tuner report      --workdir D
     python -m paper_1810_10496_amd.tuner study       --workdir D --out study.md
+    python -m paper_1810_10496_amd.tuner orders-<step> --workdir D ...  (random phase orders, tuner/orders.py)
 """
 from __future__ import annotations
 
@@ -28,7 +29,8 @@ def log(*a):
 def main(argv=None):
     ap = argparse.ArgumentParser(prog="python -m paper_1810_10496_amd.tuner")
     ap.add_argument("cmd", choices=["passes", "gpu-filter", "explore", "finalize", "reuse", "table", "report",
-                                        "study", "phase"])
+                                        "study", "phase", "orders-build", "orders-eval", "orders-finalize",
+                                        "orders-minimise", "orders-permute", "orders-cross", "orders-report"])
     ap.add_argument("--workdir", default="tune_work")
     ap.add_argument("--families", default=",".join(workloads.TUNED_FAMILIES))
     ap.add_argument("--samples", type=int, default=500)
@@ -43,6 +45,8 @@ def main(argv=None):
     ap.add_argument("--size", type=int, default=None, help="phase: the size timed (default: the largest)")
     ap.add_argument("--replays", type=int, default=10, help="phase: timed replays per variant")
     ap.add_argument("--build-only", action="store_true", help="phase: compile, do not evaluate")
+    ap.add_argument("--stage", choices=["host", "gpu"], default="host",
+                    help="orders-minimise/permute/cross: the host (compile) or the GPU (timing) half")
     a = ap.parse_args(argv)
     if a.codir:
         X.CODIR = a.codir
@@ -128,6 +132,36 @@ def main(argv=None):
         entries = tuned.read_table(a.table or tuned.TABLE)
         phase.run(fams, a.workdir, entries, a.size or max(sizes), replays=a.replays, jobs=a.jobs, log=log,
                   build_only=a.build_only)
+        return 0
+    if a.cmd.startswith("orders-"):
+        from . import orders as O
+        ofams = [f for f in a.families.split(",") if f] if a.families != ",".join(workloads.TUNED_FAMILIES) \
+            else list(O.FAMILIES)
+        if a.cmd == "orders-build":
+            O.build(ofams, a.workdir, passes.load_pool(), a.samples, a.seed if a.seed != 5500 else O.ORDER_SEED,
+                    jobs=a.jobs, log=log)
+        elif a.cmd == "orders-eval":
+            O.evaluate(ofams, a.workdir, jobs=a.jobs, log=log, max_minutes=a.max_minutes)
+        elif a.cmd == "orders-finalize":
+            O.finalize(ofams, a.workdir, log=log)
+        elif a.cmd == "orders-minimise":
+            if a.stage == "host":
+                O.minimise_host(ofams, a.workdir, jobs=a.jobs, log=log)
+            else:
+                O.minimise_gpu(ofams, a.workdir, log=log)
+        elif a.cmd == "orders-permute":
+            O.permute_host(ofams, a.workdir, jobs=a.jobs, log=log) if a.stage == "host" \
+                else O.permute_gpu(ofams, a.workdir, log=log)
+        elif a.cmd == "orders-cross":
+            O.cross_host(ofams, a.workdir, jobs=a.jobs, log=log) if a.stage == "host" \
+                else O.cross_gpu(ofams, a.workdir, log=log)
+        elif a.cmd == "orders-report":
+            text = O.report(a.workdir, ofams)
+            if a.out:
+                with open(a.out, "w") as f:
+                    f.write(text)
+            else:
+                log(text)
         return 0
     if a.cmd == "report":
         db = X.DB(os.path.join(a.workdir, "db.jsonl"))

@@ -139,12 +139,21 @@ def _evaluate(ev, db, family, sha, path, sizes, cutoff, timeout, replays=1, seed
     return rec
 
 
+class WorkerFailure(RuntimeError):
+    """A candidate killed or hung its worker; the exploration stops (stop_on_failure)."""
+
+
 def explore(family, workdir, samples=500, seed=5500, sizes=(256, 512, 1000, 2048, 4096), jobs=8,
-            eval_timeout=120.0, log=print, max_minutes=None, pool=None, make_evaluator=None, build=None):
+            eval_timeout=120.0, log=print, max_minutes=None, pool=None, make_evaluator=None, build=None,
+            variants=None, stop_on_failure=False):
+    """Compile and evaluate a family's sample (the knob sample, or `variants`: the
+    default first).  With `stop_on_failure`, the first candidate whose worker dies or
+    hangs ends the exploration (WorkerFailure): it may have faulted the GPU."""
     t_start = time.time()
     db = DB(os.path.join(workdir, "db.jsonl"))
-    pool = pool if pool is not None else passes.load_pool()
-    variants = [space.default_variant(family)] + space.sample_variants(family, pool, samples, seed)
+    if variants is None:
+        pool = pool if pool is not None else passes.load_pool()
+        variants = [space.default_variant(family)] + space.sample_variants(family, pool, samples, seed)
     compiled = {r["key"]: r for r in db.where(kind="compile", family=family)}
     evaluated = {r["sha"]: r for r in db.where(kind="eval", family=family)}
     build = build or _build
@@ -169,17 +178,25 @@ def explore(family, workdir, samples=500, seed=5500, sizes=(256, 512, 1000, 2048
                       eval_timeout)
         evaluated[rec["sha"]] = e
         done += 1
+        if stop_on_failure and e["status"] in ("crashed", "timeout"):
+            ev.close()
+            raise WorkerFailure(f"{family}: candidate {rec['sha'][:12]} {e['status']}; exploration stopped")
         big = str(max(sizes))
         tb = e["times"].get(big)
         log(f"[explore] {family} #{done} {e['status']} sha={rec['sha'][:10]} "
             f"t{big}={'%.4f' % tb if tb else '-'} pipeline={rec['variant']['pipeline'][:48]}")
 
-    # code objects compiled in an earlier (interrupted) run but never evaluated
+    # code objects compiled in an earlier (interrupted) run, or on another machine,
+    # but never evaluated
     for rec in list(compiled.values()):
         if rec["status"] == "ok" and rec["sha"] not in evaluated:
             if _ensure_co(db, workdir, family, rec["sha"]) is None:
                 continue
             eval_if_new(rec)
+            if max_minutes and time.time() - t_start > 60 * max_minutes:
+                log(f"[explore] {family}: time limit reached, stopping (resumable)")
+                ev.close()
+                return census(db, family, {v.key() for v in variants})
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         futs = [ex.submit(build, v, workdir) for v in todo]
         for fut in cf.as_completed(futs):

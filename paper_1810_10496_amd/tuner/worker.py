@@ -265,12 +265,7 @@ class Worker:
         self.reps = reps
         self.default_vid = self.ctx.variant_default(family)
         # the instances each family is timed on: its own operation at every size
-        own = {"gemm_f32": "gemm", "syrk_f32": "corr", "gemm_bf16_ws": "gemm_bf16ws",
-               "gemm_split_ws": "gemm_splitws", "syrk_bf16": "corr_bf16",
-               "syrk_split": "corr_split", "rankk": "syrk", "fdtd": "fdtd2d"}.get(family, family)
-        self.insts = [i for i in W.batch_instances(tuple(sizes)) + W.precision_instances(tuple(sizes))
-                      + W.corr_precision_instances(tuple(sizes)) + W.next_tuning_instances(tuple(sizes))
-                      if i.op == own]
+        self.insts = W.family_instances(family, tuple(sizes))
         for inst in self.insts:
             copies = max(1, min(reps, math.ceil(ROTATE_BYTES / max(inst.footprint, 1))))
             inst.state = inst.make(torch.device(DEV), copies)

@@ -293,9 +293,12 @@ def _fdtd2d(n, steps=10):
         ctx.fdtd2d(s["fict"], s["ex"][i], s["ey"][i], s["hz"][i], stream=stream)
 
     # per step and cell: E update reads hz, ey, ex and writes ey, ex; H update reads
-    # ex, ey, hz and writes hz (neighbour reads come from cache): 9 floats
+    # ex, ey, hz and writes hz (neighbour reads come from cache): 9 floats.  When the
+    # three fields fit in the 256 MB Infinity Cache they stay there across the steps
+    # of a call, and the bound is that cache's bandwidth, not HBM's
+    bound = "infinity_cache" if 12 * n * n <= (256 << 20) else "hbm"
     return Instance(f"fdtd2d/{n}x{steps}", "fdtd2d", ("fdtd",), n, 11.0 * n * n * steps,
-                    36.0 * n * n * steps, "hbm", make, run, 12 * n * n)
+                    36.0 * n * n * steps, bound, make, run, 12 * n * n)
 
 
 def next_tuning_instances(sizes=SIZES):
@@ -311,3 +314,15 @@ def next_instances():
 
 
 TUNED_FAMILIES = ("gemm_f32", "gemv", "gemv_t", "gemv_pair", "conv2d", "conv3d", "colstats", "syrk_f32")
+
+# the operation each kernel family is timed on (the family's own; a family not
+# listed is timed on the operation of the same name)
+FAMILY_OP = {"gemm_f32": "gemm", "syrk_f32": "corr", "gemm_bf16_ws": "gemm_bf16ws", "gemm_split_ws": "gemm_splitws",
+             "syrk_bf16": "corr_bf16", "syrk_split": "corr_split", "rankk": "syrk", "fdtd": "fdtd2d"}
+
+
+def family_instances(family, sizes=SIZES):
+    """The instances a kernel family is timed on: its own operation at `sizes`."""
+    op = FAMILY_OP.get(family, family)
+    return [i for i in batch_instances(tuple(sizes)) + precision_instances(tuple(sizes))
+            + corr_precision_instances(tuple(sizes)) + next_tuning_instances(tuple(sizes)) if i.op == op]

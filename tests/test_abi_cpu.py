@@ -129,7 +129,7 @@ def _lib_fn_names(fid):
              12: ["pk_convert", "pk_fill"],
              13: ["pk_rankk_syrk", "pk_rankk_syr2k"], 14: ["pk_gesummv", "pk_colsum_accumulate"],
              15: ["pk_fdtd_e", "pk_fdtd_h"], 16: ["pk_gemm_bf", "pk_gemm_prep"],
-             17: ["pk_gemm_bf", "pk_gemm_prep"]}
+             17: ["pk_gemm_bf", "pk_gemm_prep"], 18: ["pk_stream_read", "pk_stream_copy"]}
     return table[fid]
 
 

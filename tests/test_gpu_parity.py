@@ -477,3 +477,21 @@ def test_graph_replay_matches_eager(ctx):
         assert np.array_equal(h(y1), e1) and np.array_equal(h(y2), e2), rep
         assert np.array_equal(h(out), eo), rep
     graph.destroy()
+
+
+# ---------------------------------------------------------- bandwidth probes --
+
+@pytest.mark.parametrize("n", [0, 3, 4, 1001, 1 << 20, (1 << 20) + 7])
+def test_stream_probes(ctx, n):
+    """The read probe sums every element exactly once (block sums add up to the total);
+    the copy probe copies bitwise, including a ragged tail."""
+    say("stream probes", n)
+    x = synth.uniform(77, (max(n, 1),))[:n]
+    xs = g(x) if n else torch.empty(0, device=DEV)
+    sums = torch.full((api.Context.STREAM_BLOCKS,), float("nan"), device=DEV)
+    ctx.stream_probe("read", xs, sums)
+    total = float(np.sum(h(sums).astype(np.float64)))
+    assert abs(total - float(np.sum(x.astype(np.float64)))) <= 1e-5 * max(1.0, float(np.sum(x)))
+    out = torch.full((max(n, 1),), float("nan"), device=DEV)[:n]
+    ctx.stream_probe("copy", xs, out)
+    assert np.array_equal(h(out).view(np.uint32), x.view(np.uint32))

@@ -411,3 +411,98 @@ def test_gated_build_is_recorded_and_never_written(tmp_path):
     rec = X._build(v, str(tmp_path))
     assert rec["status"] == "gated" and rec["stage"] == "gate" and "src_private_base" in rec["detail"]
     assert not os.path.exists(X._co_path(str(tmp_path), v.family, rec["sha"]))
+
+
+# ------------------------------------------------------------ phase orders --
+
+from paper_1810_10496_amd.tuner import orders as O   # noqa: E402
+
+
+def test_orders_are_seeded_shared_and_extendable():
+    pool = passes.load_pool()
+    a = O.sample_orders(pool, 50)
+    assert a == O.sample_orders(pool, 50)
+    assert a != O.sample_orders(pool, 50, seed=O.ORDER_SEED + 1)
+    assert O.sample_orders(pool, 120)[:50] == a          # a larger sample extends a smaller one
+    assert all(1 <= len(o) <= O.MAX_LEN and set(o) <= set(pool) for o in a)
+    lens = [len(o) for o in O.sample_orders(pool, 400)]
+    assert min(lens) < 20 and max(lens) > 230             # uniform over 1..256
+    reps = sum(len(o) - len(set(o)) for o in a)
+    assert reps > 0                                        # repetition allowed
+    # one set for every family, at the family's default knobs
+    for fam in O.FAMILIES:
+        vs = O.sample_variants(fam, a)
+        assert [v.pipeline for v in vs] == [O.pipeline(o) for o in a]
+        assert all(v.knobs == space.default_knobs(fam) for v in vs)
+
+
+def test_permutations_keep_the_pass_instances():
+    short = ["a", "b", "b", "c"]
+    ps = O.permutations(short)
+    assert len(ps) == 11 and tuple(short) not in {tuple(p) for p in ps}     # 4!/2! - 1
+    assert all(sorted(p) == sorted(short) for p in ps)
+    long_ = [f"p{i}" for i in range(12)]
+    ps = O.permutations(long_, count=300)
+    assert len(ps) == 300 and len({tuple(p) for p in ps}) == 300
+    assert all(sorted(p) == sorted(long_) for p in ps)
+    assert O.permutations(long_, count=300) == ps           # seeded
+
+
+def test_strip_inert_keeps_exactly_the_passes_that_change_the_code(monkeypatch):
+    # stand-in for the compiler: the code depends on the subsequence of "active" passes
+    # (with their order and repetitions), every other pass changes nothing
+    active = {"sroa", "licm", "gvn"}
+    calls = []
+
+    def fake_hash(family, order):
+        calls.append(len(order))
+        return "|".join(p for p in order if p in active)
+
+    monkeypatch.setattr(O, "_hash", fake_hash)
+    order = ["dce", "sroa", "adce", "adce", "licm", "x", "gvn", "y", "licm", "z"] * 3
+    got, ref = O.strip_inert("gemv", order, jobs=2, log=lambda *a: None)
+    assert got == [p for p in order if p in active]
+    assert ref == fake_hash("gemv", order)
+    assert len(calls) < 4 * len(order)
+
+
+def test_orders_report_from_a_small_db(tmp_path):
+    wd = str(tmp_path)
+    pool = ["function(gvn)", "function(sroa)", "function(adce)"]
+    orders = O.sample_orders(pool, 6)
+    O._save(wd, "orders.json", dict(seed=O.ORDER_SEED, max_len=O.MAX_LEN, count=6, pool=pool, orders=orders))
+    db = X.DB(os.path.join(wd, "db.jsonl"))
+    fam = "gemv"
+    d = space.default_variant(fam)
+    db.add(dict(kind="eval", family=fam, sha="default", status="ok", times={"4096": 2.0}))
+    statuses = ["ok", "ok", "gated", "compile_fail", "ok", "wrong"]
+    for i, (o, st) in enumerate(zip(orders, statuses)):
+        v = O.order_variant(fam, o)
+        if st in ("gated", "compile_fail"):
+            db.add(dict(kind="compile", family=fam, key=v.key(), variant=v.to_json(), status=st))
+            continue
+        db.add(dict(kind="compile", family=fam, key=v.key(), variant=v.to_json(), status="ok", sha=f"s{i}"))
+        db.add(dict(kind="eval", family=fam, sha=f"s{i}", status="wrong_output" if st == "wrong" else "ok",
+                    times={"4096": 1.0 + i}))
+    c = O.census(wd, [fam])[fam]
+    assert c["ok"] == 3 and c["gated"] == 1 and c["compile_fail"] == 1 and c["wrong_output"] == 1
+    sp = O.sample_speedups(wd, fam)
+    assert sp[0] == 2.0 and sp[2] is None and sp[5] is None
+    text = O.report(wd, [fam])
+    assert "Census" in text and "| gemv |" in text
+
+
+def test_fixed_random_order_of_the_gpu_variant_tests_passes_the_gate():
+    """The random phase order the GPU variant tests run is order 73 of the seeded sample,
+    and with their knob settings it builds gate-passing code objects unlike -O3's."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("tv", os.path.join(HERE, "test_gpu_variants.py"))
+    tv = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(tv)
+    assert tv.ORDER == O.pipeline(O.sample_orders(passes.load_pool(), 74)[73])
+    from paper_1810_10496_amd.tuner import gate
+    for fam, knobs, pipe in tv.VARIANTS:
+        if pipe == tv.ORDER:
+            b = codegen.compile_variant(fam, knobs, pipe)
+            assert gate.check(b.code) is None, fam
+            assert b.code_hash != codegen.compile_variant(fam, knobs, "default<O3>").code_hash

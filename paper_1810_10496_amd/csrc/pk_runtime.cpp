@@ -47,7 +47,11 @@ pk_status fail(pk_status s, const char *fmt, ...) {
     return s;
 }
 
+// A failed HIP call also leaves its code as the thread's last HIP error, which the
+// caller's next unrelated check (torch's launch checks, for one) would report as its
+// own: take it off before returning the status.
 pk_status hip_fail(hipError_t e, const char *what) {
+    (void)hipGetLastError();
     return fail(PK_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
@@ -148,12 +152,15 @@ pk_status load_module(pk_context *ctx, const void *code, size_t bytes, bool buil
         return fail(PK_ERR_INVALID_ARG, "variant code object is empty");
     auto v = std::make_unique<Variant>();
     hipError_t e = hipModuleLoadData(&v->mod, code);
-    if (e != hipSuccess)
+    if (e != hipSuccess) {
+        (void)hipGetLastError();    // not the caller's error to find later (see hip_fail)
         return fail(PK_ERR_NO_VARIANT, "hipModuleLoadData: %s", hipGetErrorString(e));
+    }
     hipDeviceptr_t kp = nullptr;
     size_t ksz = 0;
     e = hipModuleGetGlobal(&kp, &ksz, v->mod, "pk_knobs");
     if (e != hipSuccess || ksz != sizeof(v->knobs)) {
+        (void)hipGetLastError();
         (void)hipModuleUnload(v->mod);
         return fail(PK_ERR_NO_VARIANT, "code object has no pk_knobs record");
     }
@@ -213,6 +220,7 @@ pk_status load_module(pk_context *ctx, const void *code, size_t bytes, bool buil
             continue;
         e = hipModuleGetFunction(&v->fn[i], v->mod, name);
         if (e != hipSuccess) {
+            (void)hipGetLastError();
             (void)hipModuleUnload(v->mod);
             return fail(PK_ERR_NO_VARIANT, "code object lacks entry point %s", name);
         }

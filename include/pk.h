@@ -231,6 +231,25 @@ pk_status pk_corr(pk_context *ctx, pk_precision prec, int64_t n, int64_t m, cons
                   int64_t ldx, float eps, float *mean, float *std, float *R, int64_t ldr,
                   void *ws, size_t ws_bytes, pk_stream stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): pk_corr without a workspace
+ * argument.  The workspace pk_corr would take is the library's own static
+ * device array of PK_NOALLOC_SCRATCH_BYTES per device, whose address is taken
+ * once per device when the first context on it is created and which is held
+ * until the process ends.  The call allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine) and otherwise behaves as pk_corr: same kernels,
+ * same results, same argument checks; X, mean, std and R are the caller's.
+ * A problem whose pk_corr workspace (pk_workspace_bytes(PK_KERNEL_CORR, {n,m},
+ * prec)) exceeds the scratch is rejected with PK_ERR_SHAPE before anything is
+ * enqueued.  Every call on one device shares that device's scratch and leaves
+ * its contents behind (each call writes all it reads), so calls that overlap
+ * on one device -- on two streams, or from two threads -- race and must be
+ * serialised by the caller. */
+#define PK_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+pk_status pk_corr_noalloc(pk_context *ctx, pk_precision prec, int64_t n, int64_t m,
+                          const float *X, int64_t ldx, float eps, float *mean, float *std,
+                          float *R, int64_t ldr, pk_stream stream);
+
 /* COVAR (Sec. 2.2; same mean kernel as CORR, Sec. 3.4): mean as pk_colstats,
  * then C = (X - mean)^T (X - mean) / (n-1), m x m, lower-triangle tiles
  * mirrored (exactly symmetric), in the requested precision.  Requires n >= 2.

@@ -40,6 +40,8 @@ SIGNATURES = [
     ("pk_colstats", c_st, [c_vp, c_i64, c_i64, c_vp, c_i64, c_f32, c_vp, c_vp, c_vp, c_sz, c_vp]),
     ("pk_corr", c_st, [c_vp, ctypes.c_int, c_i64, c_i64, c_vp, c_i64, c_f32, c_vp, c_vp, c_vp, c_i64,
                        c_vp, c_sz, c_vp]),
+    ("pk_corr_noalloc", c_st, [c_vp, ctypes.c_int, c_i64, c_i64, c_vp, c_i64, c_f32, c_vp, c_vp, c_vp, c_i64,
+                               c_vp]),
     ("pk_convert_bf16", c_st, [c_vp, c_i64, c_vp, c_vp, c_vp, c_vp]),
     ("pk_covar", c_st, [c_vp, ctypes.c_int, c_i64, c_i64, c_vp, c_i64, c_vp, c_vp, c_i64, c_vp, c_sz, c_vp]),
     ("pk_ssyrk", c_st, [c_vp, c_i64, c_i64, c_f32, c_vp, c_i64, c_f32, c_vp, c_i64, c_vp]),

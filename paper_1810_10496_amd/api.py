@@ -268,6 +268,20 @@ class Context:
                                  _ptr(std), _ptr(R), ldr, _ptr(ws), nb, _stream(stream)))
         return R, mean, std
 
+    def corr_noalloc(self, X, eps, R, mean, std, prec="fp32", stream=None):
+        """pk_corr_noalloc: the correlation into the caller's R, mean and std with the
+        library's static scratch as workspace (nothing is allocated, here or below)."""
+        ldx = _rows(X, "X")
+        n, m = X.shape
+        ldr = _rows(R, "R")
+        if tuple(R.shape) != (m, m):
+            raise ValueError("R must be m x m")
+        _vec(mean, "mean", m)
+        _vec(std, "std", m)
+        _check(self._lib.pk_corr_noalloc(self.handle, PRECISIONS[prec], n, m, _ptr(X), ldx, float(eps),
+                                         _ptr(mean), _ptr(std), _ptr(R), ldr, _stream(stream)))
+        return R, mean, std
+
     def covar(self, X, prec="fp32", C=None, mean=None, ws=None, stream=None):
         """Covariance matrix of the columns of X; returns (C, mean)."""
         ldx = _rows(X, "X")

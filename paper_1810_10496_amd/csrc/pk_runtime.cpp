@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "../../include/pk.h"
+#include "pk_internal.h"
 #include "pk_kernel_abi.h"
 
 static_assert((int)PK_FAMILY_COUNT == (int)PKF_COUNT, "family enums out of sync");
@@ -482,6 +483,67 @@ pk_status run_colstats(pk_context *ctx, int64_t n, int64_t m, const float *X, in
 
 }  // namespace
 
+// ---- shared implementations (pk_internal.h) ---------------------------------------------
+
+pk_status pk_internal_fail(pk_status s, const char *msg) { return fail(s, "%s", msg); }
+
+pk_status pk_internal_device(pk_context *ctx, int *device) {
+    PK_TRY(check_ctx(ctx));
+    *device = ctx->device;
+    return PK_OK;
+}
+
+size_t pk_internal_corr_ws(pk_precision prec, int64_t n, int64_t m) { return ws_corr(prec, n, m); }
+
+pk_status pk_internal_corr(pk_context *ctx, pk_precision prec, int64_t n, int64_t m, const float *X,
+                           int64_t ldx, float eps, float *mean, float *std_, float *R, int64_t ldr,
+                           void *ws, size_t ws_bytes, bool ws_owned, hipStream_t s) {
+    g_err.clear();
+    PK_TRY(check_ctx(ctx));
+    if (prec < PK_FP32 || prec > PK_SPLIT_BF16)
+        return fail(PK_ERR_INVALID_ARG, "bad precision %d", (int)prec);
+    if (n < 0 || m < 0)
+        return fail(PK_ERR_SHAPE, "negative size");
+    if (m > 0 && n < 2)
+        return fail(PK_ERR_SHAPE, "correlation needs n >= 2 samples");
+    if (ldx < std::max<int64_t>(m, 1) || ldr < std::max<int64_t>(m, 1))
+        return fail(PK_ERR_SHAPE, "leading dimension smaller than m");
+    if (!(eps >= 0.f))
+        return fail(PK_ERR_INVALID_ARG, "eps must be >= 0");
+    if (m == 0)
+        return PK_OK;
+    if (ws_owned && ws_corr(prec, n, m) > ws_bytes)
+        return fail(PK_ERR_SHAPE, "n = %lld, m = %lld needs %zu bytes of scratch; the library's scratch holds %zu",
+                    (long long)n, (long long)m, ws_corr(prec, n, m), ws_bytes);
+    PK_TRY(check_ptr(ctx, X, mat_bytes(n, m, ldx), "X"));
+    PK_TRY(check_ptr(ctx, mean, (size_t)m * 4, "mean"));
+    PK_TRY(check_ptr(ctx, std_, (size_t)m * 4, "std"));
+    PK_TRY(check_ptr(ctx, R, mat_bytes(m, m, ldr), "R"));
+    if (prec != PK_FP32) {
+        const size_t need = ws_corr(prec, n, m);
+        if (ws_bytes < need)
+            return fail(PK_ERR_INVALID_ARG, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+        if (!ws_owned)
+            PK_TRY(check_ptr(ctx, ws, need, "workspace"));
+        if (reinterpret_cast<uintptr_t>(ws) & 255u)
+            return fail(PK_ERR_ALIGNMENT, "workspace must be 256-byte aligned");
+        const size_t part = align256(ws_colstats(n, m));
+        PK_TRY(run_colstats(ctx, n, m, X, ldx, eps, mean, std_, ws, part, s));
+        return run_syrk_bf(ctx, prec, n, m, X, ldx, mean, std_, R, ldr, static_cast<char *>(ws) + part, s);
+    }
+    if (!ws_owned)
+        PK_TRY(check_ptr(ctx, ws, std::min(ws_bytes, ws_colstats(n, m)), "workspace"));
+    PK_TRY(run_colstats(ctx, n, m, X, ldx, eps, mean, std_, ws, ws_bytes, s));
+    const Variant *v = pick(ctx, syrk_family(prec), std::max(n, m));
+    pk_syrk_args a{};
+    a.X = X; a.mean = mean; a.std = std_; a.R = R;
+    a.n = n; a.m = m; a.ldx = ldx; a.ldr = ldr;
+    a.aligned = aligned16(X) && ldx % 4 == 0;
+    const int64_t nt = cdiv(m, v->knobs[PK_K_TM]);
+    return launch(v, 0, nt * (nt + 1) / 2, v->knobs[PK_K_THREADS], &a, sizeof a, s);
+}
+
+
 // ==========================================================================================
 // C ABI
 // ==========================================================================================
@@ -545,6 +607,10 @@ pk_status pk_context_create(int device, pk_context **out) {
             return fail(PK_ERR_NO_VARIANT, "no built-in code object for family %d", f);
     PK_HIP(hipEventCreate(&ctx->ev0));
     PK_HIP(hipEventCreate(&ctx->ev1));
+    // the allocation-free entry points' scratch: its device address is taken here, once
+    // per device; a failure is reported by those entry points, not by the context
+    (void)pk_internal_scratch_setup(device);
+    g_err.clear();
     *out = ctx.release();
     return PK_OK;
     PK_GUARD_END
@@ -907,45 +973,8 @@ pk_status pk_corr(pk_context *ctx, pk_precision prec, int64_t n, int64_t m, cons
                   float eps, float *mean, float *std_, float *R, int64_t ldr, void *ws, size_t ws_bytes,
                   pk_stream stream) {
     PK_GUARD_BEGIN
-    g_err.clear();
-    PK_TRY(check_ctx(ctx));
-    if (prec < PK_FP32 || prec > PK_SPLIT_BF16)
-        return fail(PK_ERR_INVALID_ARG, "bad precision %d", (int)prec);
-    if (n < 0 || m < 0)
-        return fail(PK_ERR_SHAPE, "negative size");
-    if (m > 0 && n < 2)
-        return fail(PK_ERR_SHAPE, "correlation needs n >= 2 samples");
-    if (ldx < std::max<int64_t>(m, 1) || ldr < std::max<int64_t>(m, 1))
-        return fail(PK_ERR_SHAPE, "leading dimension smaller than m");
-    if (!(eps >= 0.f))
-        return fail(PK_ERR_INVALID_ARG, "eps must be >= 0");
-    if (m == 0)
-        return PK_OK;
-    PK_TRY(check_ptr(ctx, X, mat_bytes(n, m, ldx), "X"));
-    PK_TRY(check_ptr(ctx, mean, (size_t)m * 4, "mean"));
-    PK_TRY(check_ptr(ctx, std_, (size_t)m * 4, "std"));
-    PK_TRY(check_ptr(ctx, R, mat_bytes(m, m, ldr), "R"));
-    hipStream_t s = (hipStream_t)stream;
-    if (prec != PK_FP32) {
-        const size_t need = ws_corr(prec, n, m);
-        if (ws_bytes < need)
-            return fail(PK_ERR_INVALID_ARG, "workspace too small: %zu < %zu bytes", ws_bytes, need);
-        PK_TRY(check_ptr(ctx, ws, need, "workspace"));
-        if (reinterpret_cast<uintptr_t>(ws) & 255u)
-            return fail(PK_ERR_ALIGNMENT, "workspace must be 256-byte aligned");
-        const size_t part = align256(ws_colstats(n, m));
-        PK_TRY(run_colstats(ctx, n, m, X, ldx, eps, mean, std_, ws, part, s));
-        return run_syrk_bf(ctx, prec, n, m, X, ldx, mean, std_, R, ldr, static_cast<char *>(ws) + part, s);
-    }
-    PK_TRY(check_ptr(ctx, ws, std::min(ws_bytes, ws_colstats(n, m)), "workspace"));
-    PK_TRY(run_colstats(ctx, n, m, X, ldx, eps, mean, std_, ws, ws_bytes, s));
-    const Variant *v = pick(ctx, syrk_family(prec), std::max(n, m));
-    pk_syrk_args a{};
-    a.X = X; a.mean = mean; a.std = std_; a.R = R;
-    a.n = n; a.m = m; a.ldx = ldx; a.ldr = ldr;
-    a.aligned = aligned16(X) && ldx % 4 == 0;
-    const int64_t nt = cdiv(m, v->knobs[PK_K_TM]);
-    return launch(v, 0, nt * (nt + 1) / 2, v->knobs[PK_K_THREADS], &a, sizeof a, s);
+    return pk_internal_corr(ctx, prec, n, m, X, ldx, eps, mean, std_, R, ldr, ws, ws_bytes, false,
+                            (hipStream_t)stream);
     PK_GUARD_END
 }
 

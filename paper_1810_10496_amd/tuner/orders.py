@@ -149,9 +149,25 @@ def evaluate(families, workdir, jobs=8, log=print, eval_timeout=120.0, max_minut
 
 
 def census(workdir, families):
+    """Outcome counts per family over the sample; compile failures are split by stage
+    into `no_ir` (opt crashed or produced nothing: the paper's "optimised IR not
+    generated") and `backend_fail` (llc or lld rejected the optimised IR)."""
     db = X.DB(os.path.join(workdir, "db.jsonl"))
     orders = load_orders(workdir)
-    return {f: X.census(db, f, {v.key() for v in sample_variants(f, orders)}) for f in families}
+    out = {}
+    for f in families:
+        keys = {v.key() for v in sample_variants(f, orders)}
+        c = X.census(db, f, keys)
+        latest = {}
+        for r in db.where(kind="compile", family=f):
+            if r["key"] in keys:
+                latest[r["key"]] = r
+        fails = [r for r in latest.values() if r["status"] == "compile_fail"]
+        c.pop("compile_fail", None)
+        c["no_ir"] = c.pop("no_output", 0) + sum(1 for r in fails if r.get("stage") in ("opt", "frontend"))
+        c["backend_fail"] = sum(1 for r in fails if r.get("stage") not in ("opt", "frontend"))
+        out[f] = c
+    return out
 
 
 def finalize(families, workdir, log=print):
@@ -489,7 +505,7 @@ def _spearman(a, b):
     return num / den if den else float("nan")
 
 
-STATUS_ORDER = ("ok", "no_output", "compile_fail", "gated", "load_fail", "wrong_output", "timeout", "crashed",
+STATUS_ORDER = ("ok", "no_ir", "backend_fail", "gated", "load_fail", "wrong_output", "timeout", "crashed",
                 "broken_report", "error", "not_evaluated")
 
 

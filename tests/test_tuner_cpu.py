@@ -479,13 +479,14 @@ def test_orders_report_from_a_small_db(tmp_path):
     for i, (o, st) in enumerate(zip(orders, statuses)):
         v = O.order_variant(fam, o)
         if st in ("gated", "compile_fail"):
-            db.add(dict(kind="compile", family=fam, key=v.key(), variant=v.to_json(), status=st))
+            db.add(dict(kind="compile", family=fam, key=v.key(), variant=v.to_json(), status=st, stage="opt"))
             continue
         db.add(dict(kind="compile", family=fam, key=v.key(), variant=v.to_json(), status="ok", sha=f"s{i}"))
         db.add(dict(kind="eval", family=fam, sha=f"s{i}", status="wrong_output" if st == "wrong" else "ok",
                     times={"4096": 1.0 + i}))
     c = O.census(wd, [fam])[fam]
-    assert c["ok"] == 3 and c["gated"] == 1 and c["compile_fail"] == 1 and c["wrong_output"] == 1
+    assert c["ok"] == 3 and c["gated"] == 1 and c["no_ir"] == 1 and c["wrong_output"] == 1
+    assert c["backend_fail"] == 0
     sp = O.sample_speedups(wd, fam)
     assert sp[0] == 2.0 and sp[2] is None and sp[5] is None
     text = O.report(wd, [fam])

@@ -30,7 +30,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser(prog="python -m paper_1810_10496_amd.tuner")
     ap.add_argument("cmd", choices=["passes", "gpu-filter", "explore", "finalize", "reuse", "table", "report",
                                         "study", "phase", "orders-build", "orders-eval", "orders-finalize",
-                                        "orders-minimise", "orders-permute", "orders-cross", "orders-report"])
+                                        "orders-minimise", "orders-permute", "orders-cross", "orders-table",
+                                        "orders-report"])
     ap.add_argument("--workdir", default="tune_work")
     ap.add_argument("--families", default=",".join(workloads.TUNED_FAMILIES))
     ap.add_argument("--samples", type=int, default=500)
@@ -155,6 +156,11 @@ def main(argv=None):
         elif a.cmd == "orders-cross":
             O.cross_host(ofams, a.workdir, jobs=a.jobs, log=log) if a.stage == "host" \
                 else O.cross_gpu(ofams, a.workdir, log=log)
+        elif a.cmd == "orders-table":
+            out = a.out or os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tuned",
+                                        "orders.json")
+            O.write_table(a.workdir, ofams, out)
+            log(f"[orders] table -> {out}")
         elif a.cmd == "orders-report":
             text = O.report(a.workdir, ofams)
             if a.out:

@@ -253,18 +253,18 @@ def minimise_host(families, workdir, jobs=8, log=print):
     return doc
 
 
-def _time_order(ev, db, workdir, family, order, size, replays, log):
-    """(status, ms) of an order compiled now, validated and timed with `replays` replays."""
+def _time_order(ev, db, workdir, family, order, size, replays, log, with_sha=False):
+    """(status, ms) of an order compiled now, validated and timed with `replays` replays
+    (and the code object's hash with `with_sha`)."""
     v = order_variant(family, order)
     rec = X._build(v, workdir)
     db.add(rec)
-    if rec["status"] != "ok":
-        return rec["status"], None
-    e = X._evaluate(ev, db, family, rec["sha"], X._co_path(workdir, family, rec["sha"]), [size], None, 300,
-                    replays=replays, validate=True)
-    if e["status"] != "ok":
-        return e["status"], None
-    return "ok", e["times"].get(str(size))
+    out = (rec["status"], None)
+    if rec["status"] == "ok":
+        e = X._evaluate(ev, db, family, rec["sha"], X._co_path(workdir, family, rec["sha"]), [size], None, 300,
+                        replays=replays, validate=True)
+        out = (e["status"], e["times"].get(str(size)) if e["status"] == "ok" else None)
+    return out + ((rec.get("sha"),) if with_sha else ())
 
 
 def minimise_gpu(families, workdir, replays=10, log=print):
@@ -299,11 +299,11 @@ def minimise_gpu(families, workdir, replays=10, log=print):
                 raise RuntimeError(f"{fam}: worker {st}; stopping")
             if not keep:
                 cur = trial
-        st, t1 = _time_order(ev, db, workdir, fam, cur, size, replays, log)
+        st, t1, sha1 = _time_order(ev, db, workdir, fam, cur, size, replays, log, with_sha=True)
         d = X._evaluate(ev, db, fam, "default", "default", [size], None, 300, replays=replays, validate=False)
         ev.close()
         m.update(minimal=cur, steps=steps, ms_same_code=t0, ms_minimal=t1, status_minimal=st,
-                 default_ms=d["times"].get(str(size)))
+                 minimal_sha256=sha1, default_ms=d["times"].get(str(size)))
         _save(workdir, "minimised.json", doc)
         log(f"[orders] {fam}: minimal order {pipeline(cur)} ({t1} ms vs {t0} ms)")
     return doc
@@ -445,6 +445,29 @@ def cross_gpu(families, workdir, replays=10, log=print):
         _save(workdir, "cross.json", doc)
         log(f"[orders] cross into {t}: " + ", ".join(f"{s}:{r['status']}" for s, r in doc[t].items()))
     return doc
+
+
+def write_table(workdir, families, path):
+    """The committed summary: per family the best order found, its minimal form and
+    that form's code object (what the benchmark times), plus the sample's census."""
+    best = _load(workdir, "best.json", {})
+    mins = _load(workdir, "minimised.json", {})
+    doc = _load(workdir, "orders.json", {})
+    fams = {}
+    for f in families:
+        b, m = best.get(f, {}), mins.get(f, {})
+        e = dict(size=b.get("size", family_size(f)), default_ms=b.get("default_ms"))
+        if b.get("order"):
+            e.update(order_found=b["order"], best_ms=b.get("best_ms"), speedup=b.get("speedup"))
+        if m.get("minimal") and m.get("status_minimal") == "ok" and m.get("minimal_sha256"):
+            e.update(order=m["minimal"], code_sha256=m["minimal_sha256"], minimal_ms=m.get("ms_minimal"),
+                     minimal_default_ms=m.get("default_ms"))
+        fams[f] = e
+    out = dict(seed=doc.get("seed"), count=doc.get("count"), max_len=doc.get("max_len"),
+               pool_size=len(doc.get("pool", [])), census=census(workdir, families), families=fams)
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1, sort_keys=True)
+    return out
 
 
 # ------------------------------------------------------------------------ report --

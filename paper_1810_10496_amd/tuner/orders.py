@@ -499,6 +499,24 @@ def sample_speedups(workdir, family, n=None):
     return out
 
 
+def wrong_orders(workdir, families):
+    """{order number: [families]} for the sampled orders whose code object gave wrong output."""
+    db = X.DB(os.path.join(workdir, "db.jsonl"))
+    orders = load_orders(workdir)
+    out = {}
+    for f in families:
+        bad = {r["sha"] for r in db.where(kind="eval", family=f, status="wrong_output")}
+        if not bad:
+            continue
+        sha_of = {}
+        for r in db.where(kind="compile", family=f, status="ok"):
+            sha_of[r["key"]] = r["sha"]
+        for i, o in enumerate(orders):
+            if sha_of.get(order_variant(f, o).key()) in bad:
+                out.setdefault(i, []).append(f)
+    return out
+
+
 def _gm(xs):
     xs = [x for x in xs if x and x > 0]
     return math.exp(sum(math.log(x) for x in xs) / len(xs)) if xs else float("nan")
@@ -553,6 +571,11 @@ def report(workdir, families) -> str:
                  f" | {c.get('distinct_code_objects', 0)} |")
     allv = sum(tot.values()) or 1
     L.append("| all (share) | " + " | ".join(f"{100.0 * tot[k] / allv:.1f}%" for k in STATUS_ORDER) + " | |")
+    wrong = wrong_orders(workdir, families)
+    if wrong:
+        L += ["", "Orders whose code gave wrong output (order number in the sample: families): " +
+              "; ".join(f"{i}: {', '.join(fs)}" for i, fs in sorted(wrong.items(), key=lambda kv: -len(kv[1])))
+              + "."]
     sp = {f: sample_speedups(workdir, f) for f in families}
     L += ["", "## Best order of the sample, and how the sample converges (Sec. 3, 3.3)", "",
           "Best speedup over the default among the first k orders (single timings).", "",

@@ -36,6 +36,14 @@ from . import gate
 
 DEV = "cuda:0"
 ROTATE_BYTES = 640 << 20
+CACHE_BYTES = 512 << 20       # rotations at least this large stream from HBM (256 MB Infinity Cache)
+PEAK_HBM = 8.0e12             # B/s
+PEAK_FP32 = 157.3e12          # flop/s
+PEAK_BF16 = 2516.6e12         # flop/s, dense
+
+
+class Implausible(RuntimeError):
+    """A measured time faster than the roofline allows."""
 TAPS2 = np.array(synth.CONV2D_TAPS, np.float32)
 
 
@@ -203,37 +211,43 @@ def _fdtd_case(NX, NY, steps=3):
 
 
 def validation_cases(family):
+    """Small cases per family: ragged shapes that exercise every tile edge, degenerate
+    ones, exact small-integer ones, and shapes that are whole multiples of every tile
+    width the family's knobs allow (so the paths without any edge run too; a miscompiled
+    edge-free loop otherwise passes every ragged case)."""
     if family == "gemm_f32":
         return [_gemm_case(65, 33, 47), _gemm_case(128, 96, 200), _gemm_case(1, 1, 1), _gemm_case(61, 70, 90, True),
-                _gemm_case(257, 129, 64)]
+                _gemm_case(257, 129, 64), _gemm_case(512, 512, 256), _gemm_case(256, 256, 128, True)]
     if family in ("gemm_bf16", "gemm_split", "gemm_bf16_ws", "gemm_split_ws"):
         prec = "bf16" if family.startswith("gemm_bf16") else "split"
         ws = None if family.endswith("_ws") else False
         return [_gemm_case(65, 33, 47, prec=prec, ws=ws), _gemm_case(300, 200, 129, prec=prec, ws=ws),
                 _gemm_case(1, 1, 1, prec=prec, ws=ws), _gemm_case(61, 70, 90, True, prec=prec, ws=ws),
-                _gemm_case(257, 129, 64, prec=prec, ws=ws)]
+                _gemm_case(257, 129, 64, prec=prec, ws=ws), _gemm_case(512, 512, 256, prec=prec, ws=ws)]
     if family in ("gemv", "gemv_t", "gemv_pair"):
         return [_gemv_case(family, 77, 130), _gemv_case(family, 1000, 257), _gemv_case(family, 3, 5),
-                _gemv_case(family, 333, 515, True)]
+                _gemv_case(family, 333, 515, True), _gemv_case(family, 512, 2048), _gemv_case(family, 1024, 512, True)]
     if family == "conv2d":
-        return [_conv2d_case(67, 131), _conv2d_case(5, 6), _conv2d_case(257, 300), _conv2d_case(40, 70, True)]
+        return [_conv2d_case(67, 131), _conv2d_case(5, 6), _conv2d_case(257, 300), _conv2d_case(40, 70, True),
+                _conv2d_case(512, 512)]
     if family == "conv3d":
-        return [_conv3d_case(17, 33, 65), _conv3d_case(3, 3, 3), _conv3d_case(20, 40, 70)]
+        return [_conv3d_case(17, 33, 65), _conv3d_case(3, 3, 3), _conv3d_case(20, 40, 70), _conv3d_case(16, 128, 512)]
     if family == "colstats":
-        return [_colstats_case(130, 70), _colstats_case(1000, 257), _colstats_case(2, 5)]
+        return [_colstats_case(130, 70), _colstats_case(1000, 257), _colstats_case(2, 5), _colstats_case(1024, 1024)]
     if family == "syrk_f32":
-        return [_corr_case(257, 129), _corr_case(130, 70), _corr_case(2, 3), _corr_case(300, 64)]
+        return [_corr_case(257, 129), _corr_case(130, 70), _corr_case(2, 3), _corr_case(300, 64), _corr_case(512, 384)]
     if family == "rankk":
         return [_rankk_case(65, 33, False), _rankk_case(130, 200, False), _rankk_case(1, 1, False),
-                _rankk_case(97, 64, True), _rankk_case(200, 17, True)]
+                _rankk_case(97, 64, True), _rankk_case(200, 17, True), _rankk_case(384, 256, False),
+                _rankk_case(256, 128, True)]
     if family == "gesummv":
-        return [_gesummv_case(77), _gesummv_case(1000), _gesummv_case(3)]
+        return [_gesummv_case(77), _gesummv_case(1000), _gesummv_case(3), _gesummv_case(2048)]
     if family == "fdtd":
-        return [_fdtd_case(67, 131), _fdtd_case(5, 6), _fdtd_case(200, 257)]
+        return [_fdtd_case(67, 131), _fdtd_case(5, 6), _fdtd_case(200, 257), _fdtd_case(512, 512)]
     if family in ("syrk_bf16", "syrk_split"):
         prec = "bf16" if family == "syrk_bf16" else "split"
         return [_corr_case(257, 129, prec), _corr_case(130, 70, prec), _corr_case(2, 3, prec),
-                _corr_case(300, 200, prec)]
+                _corr_case(300, 200, prec), _corr_case(512, 384, prec)]
     raise KeyError(family)
 
 
@@ -305,9 +319,21 @@ class Worker:
                     return worst, f"{case[0]} seed {seed}"
         return worst, ""
 
+    def floor_ms(self, inst):
+        """The fastest a correct launch of `inst` can be: its useful flops at the matrix
+        peak of its precision, and, when its rotating operand copies exceed the Infinity
+        Cache (so that every launch reads HBM), its algorithmic bytes at the HBM peak."""
+        low = any(p in self.family for p in ("bf16", "split"))
+        t = inst.flops / (PEAK_BF16 if low else PEAK_FP32)
+        if inst.bound == "hbm" and inst.footprint * inst.state.get("_copies", 1) >= CACHE_BYTES:
+            t = max(t, inst.bytes / PEAK_HBM)
+        return t * 1e3
+
     def time(self, vid, sizes, replays, cutoff):
         """ms per launch at each size; stops early when a size runs `cutoff` x slower
-        than the given default times (then larger sizes are not timed)."""
+        than the given default times (then larger sizes are not timed).  A time below
+        the size's roofline floor cannot come from code that did all the work: it raises
+        Implausible (validation on small inputs cannot see every size's paths)."""
         out = {}
         for inst in self.insts:
             if sizes and inst.size not in sizes:
@@ -320,6 +346,10 @@ class Worker:
             finally:
                 self.ctx.variant_select(self.family, -1)
             out[str(inst.size)] = t
+            floor = self.floor_ms(inst)
+            if t < 0.95 * floor:
+                raise Implausible(f"{inst.name}: {t * 1e3:.2f} us per launch, below its roofline floor "
+                                  f"{floor * 1e3:.2f} us")
             lim = cutoff.get(str(inst.size)) if cutoff else None
             if lim is not None and t > lim:
                 break
@@ -355,7 +385,10 @@ class Worker:
                         return res
                 if req.get("time", True):
                     sizes = [int(s) for s in req.get("sizes", [])]
-                    res["times"] = self.time(vid, sizes, int(req.get("replays", 1)), req.get("cutoff"))
+                    try:
+                        res["times"] = self.time(vid, sizes, int(req.get("replays", 1)), req.get("cutoff"))
+                    except Implausible as e:
+                        res.update(status="wrong_output", detail=str(e)[:300])
                 return res
             finally:
                 if loaded:

@@ -114,13 +114,16 @@ def _phase_sections(db, workdir, families, samples, seed):
                 "at 1000 (where tuning gains most) and at the largest size.",
                 "", "| family | size | " + " | ".join(f"k={k}" for k in counts) + " |",
                 "|---|---:|" + "---:|" * len(counts)] + conv
-    out += ["", "Permutations of a best sequence (the paper's last phase-order experiment) have no counterpart",
-            "here: a standard pipeline's pass order is fixed and flags have no order."]
+    out += ["", "The order of a standard pipeline's passes is fixed and flags have no order, so the paper's",
+            "permutation experiment applies to the random phase orders: orders.md."]
     return out
 
 
-def study(workdir, families, samples=500, seed=5500):
+def study(workdir, families, samples=500, seed=5500, note=None, explored=None):
+    """`explored`: the families whose exploration rows the database holds (default: all);
+    the census, attribution, pipeline and sample sections cover only those."""
     db = X.DB(os.path.join(workdir, "db.jsonl"))
+    explored = list(families) if explored is None else [f for f in families if f in explored]
     keys = {fam: {v.key() for v in _sample(fam, samples, seed)} for fam in families}
 
     def sample_compiles(fam):
@@ -130,9 +133,11 @@ def study(workdir, families, samples=500, seed=5500):
     out = ["# Variant exploration study", "",
            "Generated by `python -m paper_1810_10496_amd.tuner study` from the exploration database,",
            "the finalized per-size tables and the reuse evaluation.  Times are ms per launch.", ""]
+    if note:
+        out += [note, ""]
     # -- census
     out += ["## Census", "", "| family | variants | distinct code objects | outcomes |", "|---|---:|---:|---|"]
-    for fam in families:
+    for fam in explored:
         c = X.census(db, fam, keys[fam])
         rest = ", ".join(f"{k} {v}" for k, v in sorted(c.items()) if k not in ("variants", "distinct_code_objects"))
         out.append(f"| {fam} | {c.get('variants', 0)} | {c.get('distinct_code_objects', 0)} | {rest} |")
@@ -156,7 +161,7 @@ def study(workdir, families, samples=500, seed=5500):
             "and in both (- where the sample holds no variant of that kind; the phase-order section below",
             "times the default knobs under every standard level).", "",
             "| family | size | pipeline only | knobs only | both |", "|---|---:|---:|---:|---:|"]
-    for fam in families:
+    for fam in explored:
         dflt = codegen.FAMILIES[fam].defaults
         comp = sample_compiles(fam)
         evals = [r for r in db.where(kind="eval", family=fam, status="ok")]
@@ -179,7 +184,7 @@ def study(workdir, families, samples=500, seed=5500):
     # -- pipelines among the fastest
     out += ["", "## Pipelines among each family's ten fastest code objects (largest size)", "",
             "| family | pipeline kinds |", "|---|---|"]
-    for fam in families:
+    for fam in explored:
         comp = sample_compiles(fam)
         evals = [r for r in db.where(kind="eval", family=fam, status="ok") if r["sha"] in comp]
         big = max((s for s in SIZES if any(s in r.get("times", {}) for r in evals)), key=int, default=None)
@@ -189,7 +194,7 @@ def study(workdir, families, samples=500, seed=5500):
         cnt = collections.Counter(_pipe_kind(comp[r["sha"]]) for r in top)
         out.append(f"| {fam} | " + ", ".join(f"{k} {v}" for k, v in cnt.most_common()) + " |")
     # -- phase-order analysis (levels, flag minimisation, first 100 samples)
-    out += _phase_sections(db, workdir, families, samples, seed)
+    out += _phase_sections(db, workdir, explored, samples, seed)
     # -- transfer matrix and reuse
     rp = os.path.join(workdir, "reuse.json")
     if os.path.exists(rp):

@@ -244,3 +244,36 @@ def test_tuned_batch_graph_vs_oracle(ctx):
         for k, v in outputs(st).items():
             assert np.array_equal(v, f[k]), (inst.name, k)
     graph.destroy()
+
+
+# ------------------------------------------------------------------ phase orders --
+
+ORDERS = tuned.read_orders()
+
+
+def test_every_phase_order_entry_builds():
+    """Each minimal best order of the phase-order exploration reproduces its recorded
+    code object (the benchmark times exactly that code)."""
+    for e in ORDERS:
+        assert tuned.code_for(e) is not None, e["family"]
+
+
+@pytest.mark.parametrize("e", ORDERS, ids=[e["family"] for e in ORDERS])
+def test_phase_order_vs_oracle(ctx, e):
+    """The family's best phase order (default knobs) on the instance the benchmark times
+    it on, against the oracle."""
+    fam = e["family"]
+    vid = ctx.variant_load(tuned.code_for(e))
+    try:
+        for inst in W.family_instances(fam, (e["size"],)):
+            print("[case] phase order", fam, inst.name, flush=True)
+            ctx.variant_select(fam, vid)
+            try:
+                st, x = _run(ctx, inst)
+            finally:
+                ctx.variant_select(fam, -1)
+            err, tol = check(inst, st, x)
+            print("[case] phase order", fam, inst.name, "err", err, flush=True)
+            assert err <= tol
+    finally:
+        ctx.variant_unload(vid)

@@ -253,59 +253,77 @@ def minimise_host(families, workdir, jobs=8, log=print):
     return doc
 
 
-def _time_order(ev, db, workdir, family, order, size, replays, log, with_sha=False):
-    """(status, ms) of an order compiled now, validated and timed with `replays` replays
-    (and the code object's hash with `with_sha`)."""
-    v = order_variant(family, order)
-    rec = X._build(v, workdir)
-    db.add(rec)
-    out = (rec["status"], None)
-    if rec["status"] == "ok":
-        e = X._evaluate(ev, db, family, rec["sha"], X._co_path(workdir, family, rec["sha"]), [size], None, 300,
-                        replays=replays, validate=True)
-        out = (e["status"], e["times"].get(str(size)) if e["status"] == "ok" else None)
-    return out + ((rec.get("sha"),) if with_sha else ())
-
-
-def minimise_gpu(families, workdir, replays=10, log=print):
+def minimise_gpu(families, workdir, replays=10, jobs=16, log=print, make_evaluator=None, build=None):
     """Remove the remaining passes whose removal does not slow the kernel by more than
-    MARGIN (greedy, last to first, each removal judged against the order it starts from)."""
+    MARGIN.  Every single-pass removal is built (in parallel) and timed against the
+    order itself; the passes whose removal alone stays within MARGIN are then removed
+    together if that still stays within MARGIN, else one at a time, last to first, each
+    judged against the order it starts from."""
     doc = _load(workdir, "minimised.json", {})
     db = X.DB(os.path.join(workdir, "db_minimise.jsonl"))
+
+    build = build or X._build
+
+    def timed(ev, fam, order, size, rec=None):
+        rec = rec or build(order_variant(fam, order), workdir)
+        db.add(rec)
+        if rec["status"] != "ok":
+            return rec["status"], None, None
+        e = X._evaluate(ev, db, fam, rec["sha"], X._co_path(workdir, fam, rec["sha"]), [size], None, 300,
+                        replays=replays, validate=True)
+        if e["status"] in ("crashed", "timeout"):
+            ev.close()
+            raise X.WorkerFailure(f"{fam}: worker {e['status']}; stopping")
+        return e["status"], (e["times"].get(str(size)) if e["status"] == "ok" else None), rec["sha"]
+
     for fam in families:
         m = doc.get(fam)
         if not m or "minimal" in m:
             continue
         size = m["size"]
-        ev = Evaluator(fam, [size], log=log, stderr_path=os.path.join(workdir, f"worker_{fam}.err"))
-        st, t0 = _time_order(ev, db, workdir, fam, m["same_code"], size, replays, log)
+        ev = (make_evaluator or (lambda f, z: Evaluator(f, [z], log=log, stderr_path=os.path.join(
+            workdir, f"worker_{f}.err"))))(fam, size)
+        st, t0, _ = timed(ev, fam, m["same_code"], size)
         if st != "ok" or not t0:
             ev.close()
             m["minimal"], m["note"] = m["same_code"], f"the order itself: {st}"
             _save(workdir, "minimised.json", doc)
-            if st in ("crashed", "timeout"):
-                raise RuntimeError(f"{fam}: worker {st}; stopping")
             continue
-        cur, steps = list(m["same_code"]), []
-        for i in reversed(range(len(cur))):
-            trial = cur[:i] + cur[i + 1:]
-            if not trial:
+        cur = list(m["same_code"])
+        limit = t0 * (1.0 + MARGIN)
+        trials = [cur[:i] + cur[i + 1:] for i in range(len(cur))]
+        with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+            recs = list(ex.map(lambda o: build(order_variant(fam, o), workdir) if o else None, trials))
+        singles = []
+        for i, (o, rec) in enumerate(zip(trials, recs)):
+            if rec is None:
                 continue
-            st, t = _time_order(ev, db, workdir, fam, trial, size, replays, log)
-            keep = not (st == "ok" and t and t <= t0 * (1.0 + MARGIN))
-            steps.append(dict(removed=cur[i], status=st, ms=t, kept=keep))
-            if st in ("crashed", "timeout"):
-                ev.close()
-                raise RuntimeError(f"{fam}: worker {st}; stopping")
-            if not keep:
-                cur = trial
-        st, t1, sha1 = _time_order(ev, db, workdir, fam, cur, size, replays, log, with_sha=True)
+            st, t, _ = timed(ev, fam, o, size, rec)
+            singles.append(dict(removed=cur[i], position=i, status=st, ms=t,
+                                removable=bool(st == "ok" and t and t <= limit)))
+        drop = [x["position"] for x in singles if x["removable"]]
+        together = [p for i, p in enumerate(cur) if i not in set(drop)]
+        how = "none removable"
+        if drop and together:
+            st, t, _ = timed(ev, fam, together, size)
+            if st == "ok" and t and t <= limit:
+                cur, how = together, "removed together"
+            else:
+                how = "one at a time"
+                for i in sorted(drop, reverse=True):
+                    trial = cur[:i] + cur[i + 1:]
+                    if not trial:
+                        continue
+                    st, t, _ = timed(ev, fam, trial, size)
+                    if st == "ok" and t and t <= limit:
+                        cur = trial
+        st, t1, sha1 = timed(ev, fam, cur, size)
         d = X._evaluate(ev, db, fam, "default", "default", [size], None, 300, replays=replays, validate=False)
         ev.close()
-        m.update(minimal=cur, steps=steps, ms_same_code=t0, ms_minimal=t1, status_minimal=st,
+        m.update(minimal=cur, singles=singles, how=how, ms_same_code=t0, ms_minimal=t1, status_minimal=st,
                  minimal_sha256=sha1, default_ms=d["times"].get(str(size)))
         _save(workdir, "minimised.json", doc)
-        log(f"[orders] {fam}: minimal order {pipeline(cur)} ({t1} ms vs {t0} ms)")
+        log(f"[orders] {fam}: minimal order {pipeline(cur)} ({t1} ms vs {t0} ms, {how})")
     return doc
 
 

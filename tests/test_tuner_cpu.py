@@ -507,3 +507,28 @@ def test_fixed_random_order_of_the_gpu_variant_tests_passes_the_gate():
             b = codegen.compile_variant(fam, knobs, pipe)
             assert gate.check(b.code) is None, fam
             assert b.code_hash != codegen.compile_variant(fam, knobs, "default<O3>").code_hash
+
+
+def test_minimise_gpu_keeps_the_passes_that_pay(tmp_path):
+    """GPU half of the minimisation with a stand-in worker: the time of an order is 1.0
+    with both 'fast' passes present and 2.0 without either, so every other pass goes."""
+    wd = str(tmp_path)
+    order = ["x1", "fast1", "x2", "x3", "fast2", "x4"]
+    O._save(wd, "minimised.json", {"gemv": dict(size=4096, same_code=order)})
+
+    def fake_build(v, workdir):
+        o = v.pipeline.split(",")
+        t = 1.0 if ("fast1" in o and "fast2" in o) else 2.0
+        sha = f"t={t:.1f}_" + str(abs(hash(v.pipeline)) % 10 ** 12).rjust(12, "0")
+        p = X._co_path(workdir, v.family, sha)
+        os.makedirs(os.path.dirname(p), exist_ok=True)
+        open(p, "wb").write(b"x")
+        return dict(kind="compile", family=v.family, key=v.key(), variant=v.to_json(), status="ok", sha=sha)
+
+    mk = lambda f, z: Evaluator(f, [z], command=FAKE, start_timeout=60)
+    doc = O.minimise_gpu(["gemv"], wd, replays=1, jobs=2, log=lambda *a: None, make_evaluator=mk,
+                         build=fake_build)
+    m = doc["gemv"]
+    assert m["minimal"] == ["fast1", "fast2"]
+    assert m["how"] == "removed together"
+    assert {x["removed"] for x in m["singles"] if not x["removable"]} == {"fast1", "fast2"}

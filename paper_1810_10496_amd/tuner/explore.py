@@ -245,14 +245,16 @@ def _variant_of(db, family, sha):
 
 
 def finalize(family, workdir, sizes=(256, 512, 1000, 2048, 4096), top=10, replays=30, seeds=30,
-             eval_timeout=300.0, log=print, margin=0.03):
+             eval_timeout=300.0, log=print, margin=0.03, exclude=()):
     """Choose the variant per size bucket (or the default) and return table entries.
 
     A candidate replaces the default only if its re-timed launch is at least
     `margin` faster: microsecond launches differ by a few percent from one
-    timing to the next, and a table entry has to pay for itself."""
+    timing to the next, and a table entry has to pay for itself.  Code objects
+    whose hashes are in `exclude` do not compete."""
     db = DB(os.path.join(workdir, "db.jsonl"))
-    evals = [r for r in db.where(kind="eval", family=family, status="ok") if r["sha"] != "default"]
+    evals = [r for r in db.where(kind="eval", family=family, status="ok")
+             if r["sha"] != "default" and r["sha"] not in set(exclude)]
     ev = Evaluator(family, sizes, log=log, stderr_path=os.path.join(workdir, f"worker_{family}.err"))
     entries = []
     from ..api import Context

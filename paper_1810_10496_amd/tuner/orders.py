@@ -171,12 +171,17 @@ def census(workdir, families):
 
 
 def finalize(families, workdir, log=print):
-    """Per family, the best order at its size (30 replays, 30-seed validation) and the
-    default's time; the order is kept even when it does not beat the default."""
+    """Per family, the best sampled order at its size (30 replays, 30-seed validation) and
+    the default's time; the order is kept even when it does not beat the default (an
+    order that builds the default's own code object does not count as found)."""
     doc = _load(workdir, "best.json", {})
+    db = X.DB(os.path.join(workdir, "db.jsonl"))
     for fam in families:
         size = family_size(fam)
-        ents = X.finalize(fam, workdir, sizes=(size,), log=log, margin=-1.0)
+        # the sampled random orders compete, not the default pipeline's own code object
+        dkey = space.default_variant(fam).key()
+        own = {r["sha"] for r in db.where(kind="compile", family=fam, status="ok") if r["key"] == dkey}
+        ents = X.finalize(fam, workdir, sizes=(size,), log=log, margin=-1.0, exclude=own)
         e = ents[0]
         if e.get("is_default"):
             doc[fam] = dict(size=size, order=None, default_ms=e["default_ms"])

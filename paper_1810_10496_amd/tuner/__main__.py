@@ -152,7 +152,7 @@ def main(argv=None):
                 O.minimise_gpu(ofams, a.workdir, log=log)
         elif a.cmd == "orders-permute":
             O.permute_host(ofams, a.workdir, jobs=a.jobs, log=log) if a.stage == "host" \
-                else O.permute_gpu(ofams, a.workdir, log=log)
+                else O.permute_gpu(ofams, a.workdir, log=log, max_minutes=a.max_minutes)
         elif a.cmd == "orders-cross":
             O.cross_host(ofams, a.workdir, jobs=a.jobs, log=log) if a.stage == "host" \
                 else O.cross_gpu(ofams, a.workdir, log=log)

@@ -363,7 +363,7 @@ def _minimal(doc, fam):
 def permute_host(families, workdir, jobs=8, log=print):
     mins = _load(workdir, "minimised.json", {})
     db = X.DB(os.path.join(workdir, "db_permute.jsonl"))
-    plan = {}
+    plan = _load(workdir, "permute_plan.json", {})
     for fam in families:
         order = _minimal(mins, fam)
         if not order:
@@ -378,9 +378,15 @@ def permute_host(families, workdir, jobs=8, log=print):
     return plan
 
 
-def _eval_set(fam, workdir, dbname, variants, size, replays, log, eval_timeout=120.0):
+class TimeLimit(RuntimeError):
+    """The evaluation budget of a call ran out (resumable)."""
+
+
+def _eval_set(fam, workdir, dbname, variants, size, replays, log, eval_timeout=120.0, deadline=None):
     """Validate and time every distinct built code object of `variants` once (with
-    `replays` replays), stopping at the first worker that dies or hangs."""
+    `replays` replays), stopping at the first worker that dies or hangs; TimeLimit when
+    `deadline` (time.time()) passes first."""
+    import time
     db = X.DB(os.path.join(workdir, dbname))
     keys = {v.key() for v in variants}
     recs = {}
@@ -400,6 +406,9 @@ def _eval_set(fam, workdir, dbname, variants, size, replays, log, eval_timeout=1
         p = X._co_path(workdir, fam, sha)
         if not os.path.exists(p):
             continue
+        if deadline is not None and time.time() > deadline:
+            ev.close()
+            raise TimeLimit(f"{fam}: time limit reached (resumable)")
         e = X._evaluate(ev, db, fam, sha, p, [size], None, eval_timeout, replays=replays, validate=True)
         done[sha] = e
         if e["status"] in ("crashed", "timeout"):
@@ -417,16 +426,22 @@ def _eval_set(fam, workdir, dbname, variants, size, replays, log, eval_timeout=1
     return out
 
 
-def permute_gpu(families, workdir, replays=3, log=print):
+def permute_gpu(families, workdir, replays=3, log=print, max_minutes=None):
+    import time
     plan = _load(workdir, "permute_plan.json", {})
     doc = _load(workdir, "permuted.json", {})
+    deadline = None if max_minutes is None else time.time() + 60.0 * max_minutes
     for fam in families:
         if fam not in plan or fam in doc:
             continue
         order = plan[fam]["order"]
         size = family_size(fam)
         vs = [order_variant(fam, order)] + [order_variant(fam, p) for p in permutations(order)]
-        res = _eval_set(fam, os.path.join(workdir), "db_permute.jsonl", vs, size, replays, log)
+        try:
+            res = _eval_set(fam, workdir, "db_permute.jsonl", vs, size, replays, log, deadline=deadline)
+        except TimeLimit as e:
+            log(f"[orders] {e}")
+            return doc
         t0 = res[pipeline(order)][1]
         ratios, fails = [], {}
         for v in vs[1:]:
@@ -614,21 +629,30 @@ def report(workdir, families) -> str:
         L.append(f"| {f} | " + " | ".join(row) + " |")
     best = _load(workdir, "best.json", {})
     mins = _load(workdir, "minimised.json", {})
+    levels = _load(workdir, "phase.json", {})     # the standard levels at the default knobs (tuner phase)
     if best:
         L += ["", "## Best order per family and its minimal form (Table 1)", "",
               "Finalists re-timed with 30 replays and validated with 30 seeds; passes whose removal leaves "
               "the code object unchanged are removed on the host, then passes whose removal costs at most "
-              f"{100 * MARGIN:.0f}% are removed by timing.", "",
-              "| family | best / default (30 replays) | passes in the order | same code | minimal | minimal order |",
-              "|---|---:|---:|---:|---:|---|"]
+              f"{100 * MARGIN:.0f}% are removed by timing (10 replays).  `-OX`: the best of the standard "
+              "levels O1, O2, O3, Os at the default knobs (the paper's -OX baseline), when measured.", "",
+              "| family | best / -O3 (30 replays) | minimal / -O3 | minimal / -OX | passes in the order | "
+              "same code | minimal | minimal order |",
+              "|---|---:|---:|---:|---:|---:|---:|---|"]
         for f in families:
             b, m = best.get(f, {}), mins.get(f, {})
             if not b.get("order"):
-                L.append(f"| {f} | no order validated | | | | |")
+                L.append(f"| {f} | no order validated | | | | | | |")
                 continue
             mo = m.get("minimal")
-            L.append(f"| {f} | {b['speedup']:.3f} | {len(b['order'])} | {len(m.get('same_code', [])) or '-'} | "
-                     f"{len(mo) if mo is not None else '-'} | "
+            rmin = (f"{m['default_ms'] / m['ms_minimal']:.3f}" if m.get("default_ms") and m.get("ms_minimal")
+                    else "-")
+            lv = (levels.get(f) or {}).get("levels") or {}
+            ox = min((t for k, t in lv.items() if t and k in ("default<O1>", "default<O2>", "default<O3>",
+                                                           "default<Os>")), default=None)
+            rox = f"{ox / m['ms_minimal']:.3f}" if ox and m.get("ms_minimal") else "-"
+            L.append(f"| {f} | {b['speedup']:.3f} | {rmin} | {rox} | {len(b['order'])} | "
+                     f"{len(m.get('same_code', [])) or '-'} | {len(mo) if mo is not None else '-'} | "
                      f"{('`' + ' '.join(p for p in mo) + '`') if mo else ('(empty)' if mo == [] else '-')} |")
     perm = _load(workdir, "permuted.json", {})
     if perm:

@@ -411,6 +411,9 @@ def _eval_set(fam, workdir, dbname, variants, size, replays, log, eval_timeout=1
             raise TimeLimit(f"{fam}: time limit reached (resumable)")
         e = X._evaluate(ev, db, fam, sha, p, [size], None, eval_timeout, replays=replays, validate=True)
         done[sha] = e
+        t = e.get("times", {}).get(str(size))
+        log(f"[orders] {fam} {dbname}: {len(done)}/{len(shas)} {e['status']} {sha[:10]} "
+            f"{'%.4f ms' % t if t else ''}")
         if e["status"] in ("crashed", "timeout"):
             ev.close()
             raise RuntimeError(f"{fam}: worker {e['status']} on {sha[:12]}; stopping")

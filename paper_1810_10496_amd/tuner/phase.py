@@ -1,9 +1,9 @@
-"""Phase-order analysis of the exploration (the paper's Sec. 3.3-3.4 experiments,
-carried over to the pipelines explored here).
+"""Phase-order analysis of the knob exploration (the paper's Sec. 3.1 and 3.3
+experiments, carried over to the pipelines that exploration samples).
 
-The pipelines run on the GPU are LLVM's standard pipelines and the flags of
-their passes (random phase orders are off for GPU evaluation), so the paper's
-order-specific experiments take these forms:
+The knob exploration pairs each knob draw with a standard pipeline or the flags of
+its passes (random phase orders on fixed source are `tuner.orders`), so these
+experiments take these forms:
 
   levels     the default knobs under each standard level (O1, O2, O3, Os, Oz),
              timed at one size: how far the levels are apart (the paper finds
@@ -17,8 +17,9 @@ order-specific experiments take these forms:
              variants' speedups over the default at the largest size, the
              paper's scatter of its first 100 sequences (Sec. 3.3).
 
-Permutations of a best sequence (the paper's last experiment) have no
-counterpart: a standard pipeline's pass order is fixed, and flags have none.
+Permutations of a best sequence (the paper's last experiment) apply to the
+random orders (`tuner.orders`): a standard pipeline's pass order is fixed, and
+flags have none.
 
     python -m paper_1810_10496_amd.tuner phase --workdir D --families F --size 4096
 

@@ -256,20 +256,33 @@ def stream_ceilings(ctx, dev, stream, rounds=8):
     dsts = [torch.empty(n, device=dev) for _ in range(2)]
     torch.cuda.synchronize()
     out = {}
-    for kind in ("read", "copy"):
+    for kind in ("read", "read_nt", "copy", "copy_nt"):
         def one(r):
-            if kind == "read":
-                ctx.stream_probe("read", bufs[r % 4], sums, stream=stream)
+            if kind.startswith("read"):
+                ctx.stream_probe(kind, bufs[r % 4], sums, stream=stream)
             else:
-                ctx.stream_probe("copy", bufs[r % 4], dsts[r % 2], stream=stream)
+                ctx.stream_probe(kind, bufs[r % 4], dsts[r % 2], stream=stream)
         for r in range(4):
             one(r)
         ctx.timer_start(stream)
         for r in range(4 * rounds):
             one(r)
         ms = ctx.timer_stop(stream)
-        moved = n * 4 * (1 if kind == "read" else 2) * 4 * rounds
+        moved = n * 4 * (1 if kind.startswith("read") else 2) * 4 * rounds
         out[kind] = moved / (ms * 1e-3) / 1e9
+    # torch's own device copy, for reference
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        dsts[0].copy_(bufs[0])
+        e0.record(stream)
+        for r in range(4 * rounds):
+            dsts[r % 2].copy_(bufs[r % 4])
+        e1.record(stream)
+    e1.synchronize()
+    out["torch_copy"] = n * 4 * 2 * 4 * rounds / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    # the ceilings: the faster form of each probe
+    out["read_ceiling"] = max(out["read"], out["read_nt"])
+    out["copy_ceiling"] = max(out["copy"], out["copy_nt"], out["torch_copy"])
     del bufs, dsts
     torch.cuda.empty_cache()
     return out
@@ -379,7 +392,7 @@ def main():
     # of a buffer read once, and a copy; 512 MiB buffers in turn (2 GiB read, 1 GiB copied
     # per round), far beyond the 256 MB Infinity Cache
     ceil = stream_ceilings(ctx, dev, stream)
-    read_gbs, copy_gbs = ceil["read"], ceil["copy"]
+    read_gbs, copy_gbs = ceil["read_ceiling"], ceil["copy_ceiling"]
     log(f"HBM ceilings: read {read_gbs:.0f} GB/s, copy {copy_gbs:.0f} GB/s")
 
     # ---- per-instance default vs tuned ----------------------------------------------------------

@@ -343,7 +343,8 @@ pk_status pk_cache_flush(pk_context *ctx, pk_stream stream);
  * (not one of the paper's kernels).  kind 0 (read): every one of the n floats
  * of src is read once with 16-byte loads and dst[b] receives the sum of what
  * block b read, for b < PK_STREAM_BLOCKS (dst must hold that many floats);
- * kind 1 (copy): dst[i] = src[i] for i < n (src and dst must not overlap).
+ * kind 1 (copy): dst[i] = src[i] for i < n (src and dst must not overlap);
+ * kinds 2 and 3: the same with non-temporal loads (and stores).
  * src and dst must be 16-byte aligned (else PK_ERR_ALIGNMENT); n >= 0. */
 #define PK_STREAM_BLOCKS 2048
 pk_status pk_stream_probe(pk_context *ctx, int kind, const float *src, float *dst, int64_t n,

@@ -435,9 +435,10 @@ class Context:
     STREAM_BLOCKS = 2048     # PK_STREAM_BLOCKS
 
     def stream_probe(self, kind, src, dst, stream=None):
-        """pk_stream_probe: kind "read" (dst: STREAM_BLOCKS block sums) or "copy"."""
-        _check(self._lib.pk_stream_probe(self.handle, {"read": 0, "copy": 1}[kind], _ptr(src), _ptr(dst),
-                                         src.numel(), _stream(stream)))
+        """pk_stream_probe: kind "read" (dst: STREAM_BLOCKS block sums) or "copy", or either
+        with non-temporal accesses ("read_nt", "copy_nt")."""
+        _check(self._lib.pk_stream_probe(self.handle, {"read": 0, "copy": 1, "read_nt": 2, "copy_nt": 3}[kind],
+                                         _ptr(src), _ptr(dst), src.numel(), _stream(stream)))
         return dst
 
 

@@ -8,6 +8,8 @@
 //
 // Both walk the buffer in grid-stride order: consecutive threads take
 // consecutive 16-byte chunks, so every wavefront access is 1 KiB contiguous.
+// With `nt` set the accesses carry the non-temporal hint (streamed past the
+// caches instead of allocated in them); the caller takes the faster form.
 #include "pk_device.h"
 
 #ifndef NTHREADS
@@ -20,10 +22,24 @@
 PK_DEFINE_KNOBS(PKF_STREAM, 0, 0, 0, NTHREADS / 64, 1, 4, UNROLL, 0, 0, 0, 0, NTHREADS, 0,
                 PK_KERNEL_ABI_VERSION, 0)
 
-extern "C" __global__ void __launch_bounds__(NTHREADS) pk_stream_read(pk_stream_args a) {
-    if (blockDim.x != NTHREADS)
-        return;
-    const int64_t nv = a.n / 4;                                   // whole 16-byte chunks
+template <bool NT>
+__device__ __forceinline__ f32x4 ld(const f32x4 *p) {
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
+template <bool NT>
+__device__ __forceinline__ void st(f32x4 *p, f32x4 v) {
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
+template <bool NT>
+__device__ __forceinline__ f32x4 read_body(const pk_stream_args &a, int64_t nv) {
     const int64_t stride = (int64_t)gridDim.x * NTHREADS;
     const f32x4 *src = reinterpret_cast<const f32x4 *>(a.src);
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
@@ -32,13 +48,40 @@ extern "C" __global__ void __launch_bounds__(NTHREADS) pk_stream_read(pk_stream_
         f32x4 v[UNROLL];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
-            v[u] = src[i + u * stride];
+            v[u] = ld<NT>(src + i + u * stride);
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
             acc += v[u];
     }
     for (; i < nv; i += stride)
-        acc += src[i];
+        acc += ld<NT>(src + i);
+    return acc;
+}
+
+template <bool NT>
+__device__ __forceinline__ void copy_body(const pk_stream_args &a, int64_t nv) {
+    const int64_t stride = (int64_t)gridDim.x * NTHREADS;
+    const f32x4 *src = reinterpret_cast<const f32x4 *>(a.src);
+    f32x4 *dst = reinterpret_cast<f32x4 *>(a.dst);
+    int64_t i = (int64_t)blockIdx.x * NTHREADS + threadIdx.x;
+    for (; i + (UNROLL - 1) * stride < nv; i += UNROLL * stride) {
+        f32x4 v[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u)
+            v[u] = ld<NT>(src + i + u * stride);
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u)
+            st<NT>(dst + i + u * stride, v[u]);
+    }
+    for (; i < nv; i += stride)
+        st<NT>(dst + i, ld<NT>(src + i));
+}
+
+extern "C" __global__ void __launch_bounds__(NTHREADS) pk_stream_read(pk_stream_args a) {
+    if (blockDim.x != NTHREADS)
+        return;
+    const int64_t nv = a.n / 4;                                   // whole 16-byte chunks
+    const f32x4 acc = a.nt ? read_body<true>(a, nv) : read_body<false>(a, nv);
     float s = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     // the tail of fewer than 4 elements: block 0
     if (blockIdx.x == 0 && threadIdx.x < (int)(a.n - nv * 4))
@@ -61,21 +104,10 @@ extern "C" __global__ void __launch_bounds__(NTHREADS) pk_stream_copy(pk_stream_
     if (blockDim.x != NTHREADS)
         return;
     const int64_t nv = a.n / 4;
-    const int64_t stride = (int64_t)gridDim.x * NTHREADS;
-    const f32x4 *src = reinterpret_cast<const f32x4 *>(a.src);
-    f32x4 *dst = reinterpret_cast<f32x4 *>(a.dst);
-    int64_t i = (int64_t)blockIdx.x * NTHREADS + threadIdx.x;
-    for (; i + (UNROLL - 1) * stride < nv; i += UNROLL * stride) {
-        f32x4 v[UNROLL];
-#pragma unroll
-        for (int u = 0; u < UNROLL; ++u)
-            v[u] = src[i + u * stride];
-#pragma unroll
-        for (int u = 0; u < UNROLL; ++u)
-            dst[i + u * stride] = v[u];
-    }
-    for (; i < nv; i += stride)
-        dst[i] = src[i];
+    if (a.nt)
+        copy_body<true>(a, nv);
+    else
+        copy_body<false>(a, nv);
     if (blockIdx.x == 0 && threadIdx.x < (int)(a.n - nv * 4))
         a.dst[nv * 4 + threadIdx.x] = a.src[nv * 4 + threadIdx.x];
 }

@@ -117,6 +117,8 @@ struct pk_stream_args {
     const float *src;
     float *dst;
     int64_t n;
+    int32_t nt;        // 1: non-temporal loads and stores
+    int32_t pad_;
 };
 
 // 3x3 stencil

@@ -1413,17 +1413,18 @@ pk_status pk_stream_probe(pk_context *ctx, int kind, const float *src, float *ds
     PK_GUARD_BEGIN
     g_err.clear();
     PK_TRY(check_ctx(ctx));
-    if (kind != 0 && kind != 1)
+    if (kind < 0 || kind > 3)
         return fail(PK_ERR_INVALID_ARG, "bad probe kind %d", kind);
     if (n < 0)
         return fail(PK_ERR_SHAPE, "negative size");
     if (!aligned16(src) || !aligned16(dst))
         return fail(PK_ERR_ALIGNMENT, "probe buffers must be 16-byte aligned");
     PK_TRY(check_ptr(ctx, src, (size_t)n * 4, "src"));
-    PK_TRY(check_ptr(ctx, dst, kind == 0 ? (size_t)PK_STREAM_BLOCKS * 4 : (size_t)n * 4, "dst"));
+    const int copy = kind & 1;
+    PK_TRY(check_ptr(ctx, dst, copy ? (size_t)n * 4 : (size_t)PK_STREAM_BLOCKS * 4, "dst"));
     const Variant *v = get_variant(ctx, ctx->def[PKF_STREAM]);
-    pk_stream_args a{src, dst, n};
-    return launch(v, kind, PK_STREAM_BLOCKS, v->knobs[PK_K_THREADS], &a, sizeof a, (hipStream_t)stream);
+    pk_stream_args a{src, dst, n, kind >> 1, 0};
+    return launch(v, copy, PK_STREAM_BLOCKS, v->knobs[PK_K_THREADS], &a, sizeof a, (hipStream_t)stream);
     PK_GUARD_END
 }
 

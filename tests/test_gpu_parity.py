@@ -488,10 +488,11 @@ def test_stream_probes(ctx, n):
     say("stream probes", n)
     x = synth.uniform(77, (max(n, 1),))[:n]
     xs = g(x) if n else torch.empty(0, device=DEV)
-    sums = torch.full((api.Context.STREAM_BLOCKS,), float("nan"), device=DEV)
-    ctx.stream_probe("read", xs, sums)
-    total = float(np.sum(h(sums).astype(np.float64)))
-    assert abs(total - float(np.sum(x.astype(np.float64)))) <= 1e-5 * max(1.0, float(np.sum(x)))
-    out = torch.full((max(n, 1),), float("nan"), device=DEV)[:n]
-    ctx.stream_probe("copy", xs, out)
-    assert np.array_equal(h(out).view(np.uint32), x.view(np.uint32))
+    for nt in ("", "_nt"):
+        sums = torch.full((api.Context.STREAM_BLOCKS,), float("nan"), device=DEV)
+        ctx.stream_probe("read" + nt, xs, sums)
+        total = float(np.sum(h(sums).astype(np.float64)))
+        assert abs(total - float(np.sum(x.astype(np.float64)))) <= 1e-5 * max(1.0, float(np.sum(x)))
+        out = torch.full((max(n, 1),), float("nan"), device=DEV)[:n]
+        ctx.stream_probe("copy" + nt, xs, out)
+        assert np.array_equal(h(out).view(np.uint32), x.view(np.uint32))

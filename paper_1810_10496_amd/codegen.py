@@ -62,15 +62,15 @@ FAMILIES = {f.name: f for f in [
     _fs("gemv", 3, "gemv.hip", {"GEMV_KIND": 0},
         dict(ROWS=1, WAVES=4, VEC=4, UNROLL=4, USE_LDS=0, ORDER=0), "gemv"),
     _fs("gemv_t", 4, "gemv.hip", {"GEMV_KIND": 1},
-        dict(ROWS=64, WAVES=4, VEC=4, UNROLL=16, ORDER=0), "gemv_t"),
+        dict(ROWS=64, WAVES=4, VEC=4, UNROLL=16, ORDER=0, FUSE=0), "gemv_t"),
     _fs("gemv_pair", 5, "gemv.hip", {"GEMV_KIND": 2},
-        dict(ROWS=64, WAVES=4, VEC=4, UNROLL=16, ORDER=0), "gemv_pair"),
+        dict(ROWS=64, WAVES=4, VEC=4, UNROLL=16, ORDER=0, FUSE=0), "gemv_pair"),
     _fs("conv2d", 6, "conv.hip", {"CONV_KIND": 2},
         dict(VEC=4, TX=64, TY=4, ROWS=8, UNROLL=1, USE_LDS=0, ORDER=0), "conv2d"),
     _fs("conv3d", 7, "conv.hip", {"CONV_KIND": 3},
         dict(VEC=4, TX=64, TY=4, ROWS=16, UNROLL=1, USE_LDS=0, ORDER=0, YR=4), "conv3d"),
     _fs("colstats", 8, "colstats.hip", {},
-        dict(VEC=4, WAVES=4, ROWS=64, ORDER=0), "colstats"),
+        dict(VEC=4, WAVES=4, ROWS=64, ORDER=0, FUSE=0), "colstats"),
     _fs("syrk_f32", 9, "syrk32.hip", {},
         dict(BT=64, BK=16, WAVES_M=2, WAVES_N=2, VEC=4, STAGES=2, ORDER=0), "corr"),
     _fs("syrk_bf16", 10, "gemm_bf.hip", {"PREC": 1, "SYRK": 1},

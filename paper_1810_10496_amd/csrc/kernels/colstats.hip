@@ -27,6 +27,9 @@
 #ifndef ORDER       // 0: column strips fastest, 1: segments fastest
 #define ORDER 0
 #endif
+#ifndef FUSE        // 1: one launch (the last segment of each strip merges), 0: + pk_colstats_merge
+#define FUSE 0
+#endif
 
 constexpr int NT = 64 * WAVES;
 constexpr int RPW = (ROWS + WAVES - 1) / WAVES;
@@ -37,7 +40,14 @@ constexpr int STRIP = 64 * VEC;
 constexpr int MW = 8;
 
 PK_DEFINE_KNOBS(PKF_COLSTATS, ROWS, STRIP, ROWS, WAVES, 1, VEC, 1, 1, ORDER, 0, MW, NT,
-                3 * WAVES * STRIP * 4, PK_KERNEL_ABI_VERSION, 0)
+                3 * WAVES * STRIP * 4, PK_KERNEL_ABI_VERSION, FUSE)
+
+#if FUSE
+// partial loads in flight per thread in the one-launch merge
+constexpr int FB = 8;
+__device__ __forceinline__ void fused_merge(const pk_colstats_args &a, int strip, int seg,
+                                            float (*red)[WAVES][STRIP], float *smean);
+#endif
 
 template <int V>
 __device__ __forceinline__ void partial_body(const pk_colstats_args &a, float (*red)[WAVES][STRIP],
@@ -141,6 +151,11 @@ __device__ __forceinline__ void partial_body(const pk_colstats_args &a, float (*
     for (int e = 0; e < VEC; ++e)
         red[2][wave][lane * VEC + e] = q2[e] + qc[e];
     __syncthreads();
+#if FUSE
+    const int64_t ldp = pk_part_ld(a.m);       // one-launch layout: rows 256 bytes apart
+#else
+    const int64_t ldp = a.m;
+#endif
     for (int col = threadIdx.x; col < STRIP; col += NT) {
         float m2 = 0.f;
 #pragma unroll
@@ -148,20 +163,170 @@ __device__ __forceinline__ void partial_body(const pk_colstats_args &a, float (*
             m2 += red[2][w][col];
         const int64_t j = (int64_t)strip * STRIP + col;
         if (j < a.m) {
-            float *p = a.part + (int64_t)seg * 3 * a.m;
+            float *p = a.part + (int64_t)seg * 3 * ldp;
+#if FUSE
+            if (a.segments == 1) {        // one segment: its statistics are the column's
+                a.mean[j] = smean[col];
+                a.std[j] = fmaxf(sqrtf(m2 / (float)(a.n - 1)), a.eps);
+                continue;
+            }
+            pk_part_store(p + j, red[0][0][col]);
+            pk_part_store(p + ldp + j, red[1][0][col]);
+            pk_part_store(p + 2 * ldp + j, m2);
+#else
             p[j] = red[0][0][col];
-            p[a.m + j] = red[1][0][col];
-            p[2 * a.m + j] = m2;
+            p[ldp + j] = red[1][0][col];
+            p[2 * ldp + j] = m2;
+#endif
+        }
+    }
+#if FUSE
+    if (a.segments > 1)
+        fused_merge(a, strip, seg, red, smean);
+#endif
+}
+
+#if FUSE
+// The one-launch merge: the last segment of a strip to finish (its ticket) merges
+// the strip's segments the way pk_colstats_merge does, wavefront w taking the
+// segments b = w, w+WAVES, ... in ascending order and the WAVES results combined in
+// the order w = 0..WAVES-1: first the compensated total of every (hi, lo) term and
+// the mean from it, then M2 = sum_b [M2_b + n_b (mu_b - mu)^2].  The result does not
+// depend on which segment finishes last.
+// (hi, lo, M2) of segment b for this lane's VEC columns (vector loads when `full`)
+__device__ __forceinline__ void merge_load(const pk_colstats_args &a, int64_t ldp, int64_t c0, bool full, int b,
+                                           float (&h)[VEC], float (&l)[VEC], float (&q)[VEC]) {
+    const float *p = a.part + (int64_t)min(b, a.segments - 1) * 3 * ldp;
+    if (full) {
+        pk_part_loadv<VEC>(p + c0, h);
+        pk_part_loadv<VEC>(p + ldp + c0, l);
+        pk_part_loadv<VEC>(p + 2 * ldp + c0, q);
+    } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const bool ok = c0 + e < a.m;
+            h[e] = ok ? pk_part_load(p + c0 + e) : 0.f;
+            l[e] = ok ? pk_part_load(p + ldp + c0 + e) : 0.f;
+            q[e] = ok ? pk_part_load(p + 2 * ldp + c0 + e) : 0.f;
         }
     }
 }
+
+__device__ __forceinline__ void fused_merge(const pk_colstats_args &a, int strip, int seg,
+                                            float (*red)[WAVES][STRIP], float *smean) {
+    __shared__ int flag;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t ldp = pk_part_ld(a.m);
+    const uint32_t tag = (uint32_t)a.aligned >> 1;
+    unsigned long long *cells =
+        reinterpret_cast<unsigned long long *>(a.part + (int64_t)a.segments * 3 * ldp);
+    if (!pk_ticket_last(cells, strip, (uint32_t)seg, tag, (uint32_t)a.segments, &flag))
+        return;
+    const int64_t c0 = (int64_t)strip * STRIP + lane * VEC;
+    const bool full = c0 + VEC <= a.m && (reinterpret_cast<uintptr_t>(a.part) & 15) == 0;
+    float hi[VEC], lo[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        hi[e] = 0.f;
+        lo[e] = 0.f;
+    }
+    float hv[FB][VEC], lv[FB][VEC], mv[FB][VEC];
+    const bool one_batch = a.segments <= FB * WAVES;
+    for (int b0 = wave; b0 < a.segments; b0 += FB * WAVES) {
+#pragma unroll
+        for (int f = 0; f < FB; ++f)
+            merge_load(a, ldp, c0, full, b0 + f * WAVES, hv[f], lv[f], mv[f]);
+#pragma unroll
+        for (int f = 0; f < FB; ++f) {
+            if (b0 + f * WAVES < a.segments) {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    pk_neumaier(hi[e], lo[e], hv[f][e]);
+                    pk_neumaier(hi[e], lo[e], lv[f][e]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        red[0][wave][lane * VEC + e] = hi[e];
+        red[1][wave][lane * VEC + e] = lo[e];
+    }
+    __syncthreads();
+    for (int col = threadIdx.x; col < STRIP; col += NT) {
+        float th = 0.f, tl = 0.f;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) {
+            pk_neumaier(th, tl, red[0][w][col]);
+            pk_neumaier(th, tl, red[1][w][col]);
+        }
+        smean[col] = (th + tl) / (float)a.n;
+    }
+    __syncthreads();
+    float mu[VEC], m2[VEC], m2c[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        mu[e] = smean[lane * VEC + e];
+        m2[e] = 0.f;
+        m2c[e] = 0.f;
+    }
+    for (int b0 = wave; b0 < a.segments; b0 += FB * WAVES) {
+        if (!one_batch) {
+#pragma unroll
+            for (int f = 0; f < FB; ++f)
+                merge_load(a, ldp, c0, full, b0 + f * WAVES, hv[f], lv[f], mv[f]);
+        }
+#pragma unroll
+        for (int f = 0; f < FB; ++f) {
+            const int b = b0 + f * WAVES;
+            if (b < a.segments) {
+                const int64_t r0 = (int64_t)b * a.seg_rows;
+                const float nb = (float)(min(r0 + (int64_t)a.seg_rows, a.n) - r0);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const float d = (hv[f][e] + lv[f][e]) / nb - mu[e];
+                    pk_neumaier(m2[e], m2c[e], mv[f][e]);
+                    pk_neumaier(m2[e], m2c[e], nb * d * d);
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        red[0][wave][lane * VEC + e] = m2[e];
+        red[1][wave][lane * VEC + e] = m2c[e];
+    }
+    __syncthreads();
+    for (int col = threadIdx.x; col < STRIP; col += NT) {
+        const int64_t j = (int64_t)strip * STRIP + col;
+        if (j < a.m) {
+            float M = 0.f, Mc = 0.f;
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) {
+                pk_neumaier(M, Mc, red[0][w][col]);
+                pk_neumaier(M, Mc, red[1][w][col]);
+            }
+            a.mean[j] = smean[col];
+            a.std[j] = fmaxf(sqrtf((M + Mc) / (float)(a.n - 1)), a.eps);
+        }
+    }
+}
+#endif
 
 extern "C" __global__ void __launch_bounds__(NT) pk_colstats_partial(pk_colstats_args a) {
     if (blockDim.x != NT)
         return;
     __shared__ float red[3][WAVES][STRIP];
     __shared__ float smean[STRIP];
-    if (VEC > 1 && a.aligned)
+#if FUSE
+    const bool aligned = (a.aligned & 1) != 0;     // the upper bits carry the ticket tag
+#else
+    const bool aligned = a.aligned != 0;
+#endif
+    if (VEC > 1 && aligned)
         partial_body<VEC>(a, red, smean);
     else
         partial_body<1>(a, red, smean);

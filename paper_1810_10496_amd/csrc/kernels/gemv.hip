@@ -33,6 +33,9 @@
 #ifndef ORDER         // kinds 1/2: 0 = column strips fastest, 1 = row blocks fastest
 #define ORDER 0
 #endif
+#ifndef FUSE          // kinds 1/2: 1 = one launch (the partials are folded by the last
+#define FUSE 0        // block of each strip / row block), 0 = partials + pk_colsum_reduce
+#endif
 
 constexpr int NT = 64 * WAVES;
 constexpr int XMAX = 4096;   // x staged in LDS when N <= XMAX
@@ -48,11 +51,18 @@ constexpr int XMAX = 4096;   // x staged in LDS when N <= XMAX
 // wavefronts per block of the partial-sum reduce (kinds 1/2, pk_colsum_reduce)
 constexpr int RW = 8;
 
+#if FUSE && GEMV_KIND == 0
+#error "FUSE applies to the transposed matvec and the pair only"
+#endif
+
 // TM: rows per wavefront (kind 0) or per block (kinds 1/2); TN: columns per
-// block (kinds 1/2); X1: columns per wavefront (rows of the pair's part1 = N / X1);
-// X2: the reduce's wavefronts per block (kinds 1/2), which the runtime launches with
-PK_DEFINE_KNOBS(FAMILY, ROWS, (GEMV_KIND) == 0 ? 64 * VEC : WAVES * 64 * VEC, 0, WAVES, 1, VEC, UNROLL,
-                USE_LDS, ORDER, 64 * VEC, (GEMV_KIND) == 0 ? 0 : RW, NT, 0, PK_KERNEL_ABI_VERSION, 0)
+// block (kinds 1/2; one wavefront wide in the one-launch form, whose wavefronts
+// share the block's columns); X1: columns per wavefront (rows of the pair's part1
+// = N / X1); X2: the reduce's wavefronts per block (kinds 1/2), which the runtime
+// launches with; X3: FUSE
+PK_DEFINE_KNOBS(FAMILY, ROWS, (GEMV_KIND) == 0 ? 64 * VEC : (FUSE ? 64 * VEC : WAVES * 64 * VEC), 0, WAVES, 1,
+                VEC, UNROLL, USE_LDS, ORDER, 64 * VEC, (GEMV_KIND) == 0 ? 0 : RW, NT, 0, PK_KERNEL_ABI_VERSION,
+                FUSE)
 
 #if GEMV_KIND == 0
 // ---------------------------------------------------------------- y = A x --
@@ -268,6 +278,217 @@ __device__ __forceinline__ void colblock_body(const pk_gemvt_args &a) {
     }
 }
 
+#if FUSE
+// ------------------------------------------------------------ one launch --
+// The block is WAVES wavefronts stacked over ROWS rows of one strip of SW = 64*VEC
+// columns: wavefront w takes the block's rows w, w+WAVES, ... (RC of them in flight).
+// The wavefronts' column sums are added through LDS in the order w = 0..WAVES-1 and
+// stored as the block's row of part2; for the pair, each row's dot product over the
+// strip goes to part1[strip][row].  Then the block takes a ticket for its strip: the
+// last of the strip's row blocks adds the strip's part2 rows into y2 (wavefront w the
+// rows k = w, w+WAVES, ... in ascending order, then the WAVES sums in order w = 0..).
+// For the pair it also takes a ticket for its row block: the last of the row block's
+// strips adds part1's strips into y1 the same way.  Bit 1 of `aligned` adds the
+// results to y1 / y2 instead of storing them.
+constexpr int SW = 64 * VEC;
+constexpr int RPW = ROWS / WAVES;     // rows per wavefront
+constexpr int FB = 16;                // partial loads in flight per thread in a fold
+static_assert(ROWS % WAVES == 0 && RPW % RC == 0, "one launch: ROWS / WAVES must be a multiple of UNROLL");
+#if GEMV_KIND == 2
+constexpr int RT = NT < ROWS ? NT : ROWS;   // y1 fold: threads along the rows
+constexpr int G = NT / RT;                  // y1 fold: groups of strips
+#endif
+
+template <int V>
+__device__ __forceinline__ void fused_body(const pk_gemvt_args &a) {
+    __shared__ __attribute__((aligned(16))) float red[WAVES][SW];
+#if GEMV_KIND == 2
+    __shared__ float red1[G][ROWS];
+#endif
+    __shared__ int flag;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int strips = (int)((a.N + SW - 1) / SW);
+    int strip, rb;
+    if (ORDER == 0) {
+        strip = blockIdx.x % strips;
+        rb = blockIdx.x / strips;
+    } else {
+        rb = blockIdx.x % a.row_blocks;
+        strip = blockIdx.x / a.row_blocks;
+    }
+    if (rb >= a.row_blocks || strip >= strips)
+        return;                                          // never taken: the grid is exact
+    const bool accumulate = (a.aligned & 2) != 0;
+    const int64_t ldp = pk_part_ld(a.N);
+    const int64_t c0 = (int64_t)strip * SW + lane * VEC;
+    const bool full = c0 + VEC <= a.N;
+    const int64_t r0 = (int64_t)rb * ROWS;
+    const int64_t rend = min(r0 + (int64_t)ROWS, a.M);
+
+    float acc2[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e)
+        acc2[e] = 0.f;
+#if GEMV_KIND == 2
+    float xv[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e)
+        xv[e] = (c0 + e < a.N) ? a.x[c0 + e] : 0.f;
+#endif
+    for (int q0 = 0; q0 < RPW; q0 += RC) {
+        if (r0 + wave + (int64_t)q0 * WAVES >= rend)
+            break;                                       // wavefront-uniform
+#if GEMV_KIND == 2
+        float rs[RC];
+#endif
+#pragma unroll
+        for (int q = 0; q < RC; ++q) {
+            const int64_t i = r0 + wave + (int64_t)(q0 + q) * WAVES;
+            float av[VEC];
+            float zi = 0.f;
+            if (i < rend) {
+                zi = a.z[i];
+                if (full) {
+#pragma unroll
+                    for (int e = 0; e < VEC; e += V)
+                        pk_ldv<V>(a.A + i * a.lda + c0 + e, av + e);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e)
+                        av[e] = (c0 + e < a.N) ? a.A[i * a.lda + c0 + e] : 0.f;
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e)
+                    av[e] = 0.f;
+            }
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+                acc2[e] += av[e] * zi;
+#if GEMV_KIND == 2
+            float t = 0.f;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+                t += av[e] * xv[e];
+            rs[q] = t;
+#endif
+        }
+#if GEMV_KIND == 2
+        const float s = rows_reduce(rs, lane);
+        const int64_t i = r0 + wave + (int64_t)(q0 + (lane >> (6 - LOGR))) * WAVES;
+        if ((lane & ((1 << (6 - LOGR)) - 1)) == 0 && i < rend) {
+            if (strips == 1)                              // one strip: the dot product is y1's
+                a.y1[i] = accumulate ? a.y1[i] + s : s;
+            else
+                pk_part_store(a.part1 + (int64_t)strip * a.M + i, s);
+        }
+#endif
+    }
+
+    // the block's column sums: wavefronts added in order, one row of part2 (with one
+    // row block they are y2 itself, and no group needs a ticket)
+    const bool single = a.row_blocks == 1;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e)
+        red[wave][lane * VEC + e] = acc2[e];
+    __syncthreads();
+    for (int col = threadIdx.x; col < SW; col += NT) {
+        float t = 0.f;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w)
+            t += red[w][col];
+        const int64_t j = (int64_t)strip * SW + col;
+        if (j < a.N) {
+            if (single)
+                a.y2[j] = accumulate ? a.y2[j] + t : t;
+            else
+                pk_part_store(a.part2 + (int64_t)rb * ldp + j, t);
+        }
+    }
+    unsigned long long *cells = reinterpret_cast<unsigned long long *>(a.part2 + (int64_t)a.row_blocks * ldp);
+
+    if (!single && pk_ticket_last(cells, strip, (uint32_t)rb, a.tag, (uint32_t)a.row_blocks, &flag)) {
+        const bool pal = (reinterpret_cast<uintptr_t>(a.part2) & 15) == 0;
+        float t[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+            t[e] = 0.f;
+        for (int k0 = wave; k0 < a.row_blocks; k0 += FB * WAVES) {
+            float v[FB][VEC];
+#pragma unroll
+            for (int f = 0; f < FB; ++f) {
+                const int k = k0 + f * WAVES;
+                const float *p = a.part2 + (int64_t)min(k, a.row_blocks - 1) * ldp;
+                if (full && pal) {
+                    pk_part_loadv<VEC>(p + c0, v[f]);    // rows start 256 bytes apart
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e)
+                        v[f][e] = (c0 + e < a.N) ? pk_part_load(p + c0 + e) : 0.f;
+                }
+            }
+#pragma unroll
+            for (int f = 0; f < FB; ++f) {
+                if (k0 + f * WAVES < a.row_blocks) {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e)
+                        t[e] += v[f][e];
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+            red[wave][lane * VEC + e] = t[e];
+        __syncthreads();
+        for (int col = threadIdx.x; col < SW; col += NT) {
+            float u = 0.f;
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w)
+                u += red[w][col];
+            const int64_t j = (int64_t)strip * SW + col;
+            if (j < a.N)
+                a.y2[j] = accumulate ? a.y2[j] + u : u;
+        }
+    }
+#if GEMV_KIND == 2
+    if (strips > 1 && pk_ticket_last(cells, strips + rb, (uint32_t)strip, a.tag, (uint32_t)strips, &flag)) {
+        const int rt = threadIdx.x % RT;
+        const int g = threadIdx.x / RT;
+        for (int j = rt; j < ROWS; j += RT) {
+            const int64_t i = r0 + j;
+            float u = 0.f;
+            if (i < rend) {
+                for (int s0 = g; s0 < strips; s0 += FB * G) {
+                    float v[FB];
+#pragma unroll
+                    for (int f = 0; f < FB; ++f)
+                        v[f] = pk_part_load(a.part1 + (int64_t)min(s0 + f * G, strips - 1) * a.M + i);
+#pragma unroll
+                    for (int f = 0; f < FB; ++f)
+                        if (s0 + f * G < strips)
+                            u += v[f];
+                }
+            }
+            red1[g][j] = u;
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < ROWS; j += NT) {
+            const int64_t i = r0 + j;
+            if (i < rend) {
+                float u = 0.f;
+#pragma unroll
+                for (int q = 0; q < G; ++q)
+                    u += red1[q][j];
+                a.y1[i] = accumulate ? a.y1[i] + u : u;
+            }
+        }
+    }
+#endif
+}
+#endif
+
 #if GEMV_KIND == 1
 extern "C" __global__ void __launch_bounds__(NT) pk_gemvt_partial(pk_gemvt_args a) {
 #else
@@ -275,10 +496,17 @@ extern "C" __global__ void __launch_bounds__(NT) pk_gemv_pair_partial(pk_gemvt_a
 #endif
     if (blockDim.x != NT)
         return;
+#if FUSE
+    if (VEC > 1 && (a.aligned & 1))
+        fused_body<VEC>(a);
+    else
+        fused_body<1>(a);
+#else
     if (VEC > 1 && a.aligned)
         colblock_body<VEC>(a);
     else
         colblock_body<1>(a);
+#endif
 }
 
 // y[j] = sum_r P[r][j].  A block is RW wavefronts over 64 columns (lane = column):

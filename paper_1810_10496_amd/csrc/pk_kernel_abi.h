@@ -30,10 +30,16 @@ enum {
     PK_K_LDS_BYTES = 13,
     PK_K_ABI = 14,     // PK_KERNEL_ABI_VERSION
     PK_K_X3 = 15       // family-specific: bf16 GEMM / rank-k families: source rows per block
-                       // of the transposing operand preparation (0 means 64)
+                       // of the transposing operand preparation (0 means 64); transposed
+                       // matvec, pair and column statistics: 1 = one launch (the last
+                       // block of each group folds the partials), 0 = partials + reduce
 };
 
 #define PK_KERNEL_ABI_VERSION 3
+
+// bytes between the ticket cells of the one-launch reductions (transposed matvec,
+// pair, column statistics): one cache line and channel per group
+#define PK_CELL_STRIDE 256
 
 // kernel families: one code object implements one family
 enum pk_family_id {
@@ -92,10 +98,11 @@ struct pk_gemvt_args {
     float *part1;       // pair only: [col_strips][M]
     float *part2;       // [row_blocks][N]
     int64_t M, N, lda;
-    int32_t aligned;
+    int32_t aligned;    // bit 0: rows of A start 16-byte aligned; bit 1 (one-launch variants):
+                        // add the results to y1 / y2 instead of storing them (MVT's x += A y)
     int32_t row_blocks; // number of row blocks (rows of part2)
     int32_t col_strips; // number of column strips (rows of part1)
-    int32_t pad_;
+    uint32_t tag;       // one-launch variants: the call's ticket tag (never 0)
 };
 
 // fixed-order column sums of a partial-sum matrix: y[j] = sum_r P[r][j]
@@ -149,7 +156,8 @@ struct pk_colstats_args {
     float eps;
     int32_t segments;
     int32_t seg_rows;  // rows per segment
-    int32_t aligned;
+    int32_t aligned;   // bit 0: rows of X start 16-byte aligned; bits 1-31 (one-launch
+                       // variants): the call's ticket tag (never 0)
 };
 
 // R = Z^T Z / (n-1), Z = (X - mean) / std, lower-triangle tiles mirrored

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -188,11 +189,14 @@ pk_status load_module(pk_context *ctx, const void *code, size_t bytes, bool buil
             ok = k[PK_K_TM] >= 1 && k[PK_K_WAVES_M] >= 1;
             break;
         case PKF_GEMV_T: case PKF_GEMV_PAIR:
+            // one-launch variants (X3 = 1) are one wavefront strip wide
             ok = k[PK_K_TM] >= kMinRowBlock && k[PK_K_TN] >= kMinStrip && k[PK_K_X1] >= kMinStrip &&
-                 k[PK_K_TN] % k[PK_K_X1] == 0 && k[PK_K_X2] * 64 == kReduceThreads;
+                 k[PK_K_TN] % k[PK_K_X1] == 0 && k[PK_K_X2] * 64 == kReduceThreads &&
+                 (k[PK_K_X3] == 0 || (k[PK_K_X3] == 1 && k[PK_K_TN] == k[PK_K_X1]));
             break;
         case PKF_COLSTATS:
-            ok = k[PK_K_TM] >= kMinRowBlock && k[PK_K_TN] >= kMinStrip && k[PK_K_X2] * 64 == kReduceThreads;
+            ok = k[PK_K_TM] >= kMinRowBlock && k[PK_K_TN] >= kMinStrip && k[PK_K_X2] * 64 == kReduceThreads &&
+                 (k[PK_K_X3] == 0 || k[PK_K_X3] == 1);
             break;
         case PKF_CONV2D: case PKF_CONV3D:
             ok = k[PK_K_TM] >= 1 && k[PK_K_TN] >= 1 && k[PK_K_TK] >= 1;
@@ -337,12 +341,72 @@ pk_status check_ctx(pk_context *ctx) {
 
 // ---- workspace bounds ------------------------------------------------------------------
 
-size_t ws_gemv_t(int64_t M, int64_t N) { return (size_t)cdiv(M, kMinRowBlock) * (size_t)N * 4; }
-size_t ws_gemv_pair(int64_t M, int64_t N) {
-    return ws_gemv_t(M, N) + (size_t)cdiv(N, kMinStrip) * (size_t)M * 4;
-}
-size_t ws_colstats(int64_t n, int64_t m) { return (size_t)cdiv(n, kMinRowBlock) * 3 * (size_t)m * 4; }
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+// bytes per ticket cell of the one-launch reductions
+constexpr size_t kCellStride = PK_CELL_STRIDE;
+// row stride of the partial-sum rows: rows start 256 bytes apart (the one-launch
+// variants read them back with 16-byte loads); matches the kernels' pk_part_ld
+int64_t part_ld(int64_t n) { return (n + 63) & ~(int64_t)63; }
+
+// Transposed matvec / pair workspace: [part2: rb rows of part_ld(N)][ticket cells:
+// one per column strip (+ one per row block for the pair), PK_CELL_STRIDE bytes
+// apart][part1 (pair): wstrips rows of M].  The bound covers every variant (row
+// blocks of at least kMinRowBlock rows, strips of at least kMinStrip columns).
+struct GemvtLayout {
+    size_t part2, cells, part1;
+    size_t total() const { return part2 + cells + part1; }
+};
+GemvtLayout gemvt_layout(bool pair, int64_t M, int64_t N, int64_t rb, int64_t strips, int64_t wstrips) {
+    GemvtLayout l;
+    l.part2 = align256((size_t)rb * (size_t)part_ld(N) * 4);
+    l.cells = (size_t)(strips + (pair ? rb : 0)) * kCellStride;
+    l.part1 = pair ? (size_t)wstrips * (size_t)M * 4 : 0;
+    return l;
+}
+size_t ws_gemv_t(int64_t M, int64_t N) {
+    return gemvt_layout(false, M, N, cdiv(M, kMinRowBlock), cdiv(N, kMinStrip), 0).total();
+}
+size_t ws_gemv_pair(int64_t M, int64_t N) {
+    const int64_t rb = cdiv(M, kMinRowBlock), st = cdiv(N, kMinStrip);
+    return gemvt_layout(true, M, N, rb, st, st).total();
+}
+// Column statistics workspace: [segments][3][part_ld(m)] partials, then one ticket
+// cell per column strip (PK_CELL_STRIDE bytes apart)
+size_t colstats_bytes(int64_t segs, int64_t m, int64_t strips) {
+    return align256((size_t)segs * 3 * (size_t)part_ld(m) * 4) + (size_t)strips * kCellStride;
+}
+size_t ws_colstats(int64_t n, int64_t m) { return colstats_bytes(cdiv(n, kMinRowBlock), m, cdiv(m, kMinStrip)); }
+
+// The ticket tag of one call of a one-launch reduction: distinct for every call of
+// the process (a bijective mix of a counter, so consecutive calls differ in every
+// bit), never 0 (a cleared ticket cell holds tag 0).  `bits` 32 or 31.
+uint32_t next_tag(int bits) {
+    static std::atomic<uint32_t> counter{0};
+    const uint32_t mask = bits >= 32 ? 0xffffffffu : ((1u << bits) - 1u);
+    for (;;) {
+        uint32_t x = counter.fetch_add(1, std::memory_order_relaxed) + 1u;
+        x ^= x >> 16; x *= 0x7feb352du; x ^= x >> 15; x *= 0x846ca68bu; x ^= x >> 16;
+        x &= mask;
+        if (x != 0)
+            return x;
+    }
+}
+bool one_launch(const Variant *v) { return v->knobs[PK_K_X3] == 1; }
+
+// a one-launch variant needs its workspace 16-byte aligned (64-bit ticket cells,
+// 16-byte partial loads); with a less aligned workspace the family's built-in
+// default (partials + reduce) runs instead
+pk_status one_launch_ok(pk_context *ctx, const Variant *&v, int family, const void *ws) {
+    if (!v)
+        return fail(PK_ERR_NO_VARIANT, "no variant for family %d", family);
+    if (!one_launch(v) || (reinterpret_cast<uintptr_t>(ws) & 15u) == 0)
+        return PK_OK;
+    const Variant *d = get_variant(ctx, ctx->def[family]);
+    if (!d || one_launch(d))
+        return fail(PK_ERR_ALIGNMENT, "this variant needs a 16-byte aligned workspace");
+    v = d;
+    return PK_OK;
+}
 size_t ws_covar(int64_t n, int64_t m) { return align256(ws_colstats(n, m)) + 2 * align256((size_t)m * 4); }
 
 // ---- launches ----------------------------------------------------------------------------
@@ -465,10 +529,11 @@ pk_status run_colstats(pk_context *ctx, int64_t n, int64_t m, const float *X, in
     const Variant *v = pick(ctx, PKF_COLSTATS, std::max(n, m));
     if (!v)
         return fail(PK_ERR_NO_VARIANT, "no colstats variant");
+    PK_TRY(one_launch_ok(ctx, v, PKF_COLSTATS, ws));
     const int rows = v->knobs[PK_K_TM];
     const int64_t segs = cdiv(n, rows);
     const int64_t strips = cdiv(m, v->knobs[PK_K_TN]);
-    if ((size_t)segs * 3 * (size_t)m * 4 > ws_bytes)
+    if (colstats_bytes(segs, m, strips) > ws_bytes)
         return fail(PK_ERR_INVALID_ARG, "workspace too small for colstats");
     if (segs > 0x7fffffff)
         return fail(PK_ERR_SHAPE, "too many segments");
@@ -477,6 +542,10 @@ pk_status run_colstats(pk_context *ctx, int64_t n, int64_t m, const float *X, in
     a.n = n; a.m = m; a.ldx = ldx; a.eps = eps;
     a.segments = (int32_t)segs; a.seg_rows = rows;
     a.aligned = aligned16(X) && ldx % 4 == 0;
+    if (one_launch(v)) {
+        a.aligned |= (int32_t)(next_tag(31) << 1);
+        return launch(v, 0, segs * strips, v->knobs[PK_K_THREADS], &a, sizeof a, s);
+    }
     PK_TRY(launch(v, 0, segs * strips, v->knobs[PK_K_THREADS], &a, sizeof a, s));
     return launch(v, 1, std::min<int64_t>(cdiv(m, 64), 65535), kReduceThreads, &a, sizeof a, s);
 }
@@ -834,14 +903,15 @@ static pk_status gemvt_common(pk_context *ctx, bool pair, int64_t M, int64_t N, 
         return fail(PK_ERR_SHAPE, "lda smaller than N");
     if (M == 0 && N == 0)
         return PK_OK;
-    const Variant *v = pick(ctx, pair ? PKF_GEMV_PAIR : PKF_GEMV_T, std::max(M, N));
+    const int family = pair ? PKF_GEMV_PAIR : PKF_GEMV_T;
+    const Variant *v = pick(ctx, family, std::max(M, N));
+    PK_TRY(one_launch_ok(ctx, v, family, ws));
     const int64_t rb = cdiv(M, v->knobs[PK_K_TM]);
     const int64_t strips = cdiv(N, v->knobs[PK_K_TN]);       // blocks per row block
     const int64_t wstrips = cdiv(N, v->knobs[PK_K_X1]);      // wavefront strips (rows of part1)
-    const size_t part2 = (size_t)rb * (size_t)N * 4;
-    const size_t part1 = pair ? (size_t)wstrips * (size_t)M * 4 : 0;
-    if (ws_bytes < part1 + part2)
-        return fail(PK_ERR_INVALID_ARG, "workspace too small: %zu < %zu bytes", ws_bytes, part1 + part2);
+    const GemvtLayout lay = gemvt_layout(pair, M, N, rb, strips, wstrips);
+    if (ws_bytes < lay.total())
+        return fail(PK_ERR_INVALID_ARG, "workspace too small: %zu < %zu bytes", ws_bytes, lay.total());
     PK_TRY(check_ptr(ctx, A, mat_bytes(M, N, lda), "A"));
     PK_TRY(check_ptr(ctx, z, (size_t)M * 4, "z"));
     PK_TRY(check_ptr(ctx, y2, (size_t)N * 4, "y2"));
@@ -849,7 +919,7 @@ static pk_status gemvt_common(pk_context *ctx, bool pair, int64_t M, int64_t N, 
         PK_TRY(check_ptr(ctx, x, (size_t)N * 4, "x"));
         PK_TRY(check_ptr(ctx, y1, (size_t)M * 4, "y1"));
     }
-    PK_TRY(check_ptr(ctx, ws, part1 + part2, "workspace"));
+    PK_TRY(check_ptr(ctx, ws, lay.total(), "workspace"));
     if (M == 0 || N == 0) {
         // degenerate: y2 (length N) is all zero when M == 0; y1 (length M) when N == 0.
         // Use the reduce kernel with zero rows, which writes zeros.
@@ -863,11 +933,15 @@ static pk_status gemvt_common(pk_context *ctx, bool pair, int64_t M, int64_t N, 
     pk_gemvt_args a{};
     a.A = A; a.x = x; a.z = z; a.y1 = y1; a.y2 = y2;
     a.part2 = (float *)ws;
-    a.part1 = pair ? (float *)((char *)ws + part2) : nullptr;
+    a.part1 = pair ? (float *)((char *)ws + lay.part2 + lay.cells) : nullptr;
     a.M = M; a.N = N; a.lda = lda;
     a.aligned = aligned16(A) && lda % 4 == 0;
     a.row_blocks = (int32_t)rb;
     a.col_strips = (int32_t)wstrips;
+    if (one_launch(v)) {
+        a.tag = next_tag(32);
+        return launch(v, 0, rb * strips, v->knobs[PK_K_THREADS], &a, sizeof a, s);
+    }
     PK_TRY(launch(v, 0, rb * strips, v->knobs[PK_K_THREADS], &a, sizeof a, s));
     pk_reduce_args r{};
     r.P1 = a.part2; r.y1 = y2; r.n1 = N; r.rows1 = (int32_t)rb;
@@ -1149,19 +1223,19 @@ pk_status pk_smvt(pk_context *ctx, int64_t N, const float *A, int64_t lda, const
     if (N == 0)
         return PK_OK;
     const Variant *v = pick(ctx, PKF_GEMV_PAIR, N);
+    PK_TRY(one_launch_ok(ctx, v, PKF_GEMV_PAIR, ws));
     const int64_t rb = cdiv(N, v->knobs[PK_K_TM]);
     const int64_t strips = cdiv(N, v->knobs[PK_K_TN]);
     const int64_t wstrips = cdiv(N, v->knobs[PK_K_X1]);
-    const size_t part2 = (size_t)rb * (size_t)N * 4;
-    const size_t part1 = (size_t)wstrips * (size_t)N * 4;
-    if (ws_bytes < part1 + part2)
-        return fail(PK_ERR_INVALID_ARG, "workspace too small: %zu < %zu bytes", ws_bytes, part1 + part2);
+    const GemvtLayout lay = gemvt_layout(true, N, N, rb, strips, wstrips);
+    if (ws_bytes < lay.total())
+        return fail(PK_ERR_INVALID_ARG, "workspace too small: %zu < %zu bytes", ws_bytes, lay.total());
     PK_TRY(check_ptr(ctx, A, mat_bytes(N, N, lda), "A"));
     PK_TRY(check_ptr(ctx, y1, (size_t)N * 4, "y1"));
     PK_TRY(check_ptr(ctx, y2, (size_t)N * 4, "y2"));
     PK_TRY(check_ptr(ctx, x1, (size_t)N * 4, "x1"));
     PK_TRY(check_ptr(ctx, x2, (size_t)N * 4, "x2"));
-    PK_TRY(check_ptr(ctx, ws, part1 + part2, "workspace"));
+    PK_TRY(check_ptr(ctx, ws, lay.total(), "workspace"));
     if (rb > 0x7fffffff || wstrips > 0x7fffffff)
         return fail(PK_ERR_SHAPE, "problem too large");
     hipStream_t s = (hipStream_t)stream;
@@ -1169,11 +1243,18 @@ pk_status pk_smvt(pk_context *ctx, int64_t N, const float *A, int64_t lda, const
     pk_gemvt_args a{};
     a.A = A; a.x = y1; a.z = y2; a.y1 = nullptr; a.y2 = nullptr;
     a.part2 = (float *)ws;
-    a.part1 = (float *)((char *)ws + part2);
+    a.part1 = (float *)((char *)ws + lay.part2 + lay.cells);
     a.M = N; a.N = N; a.lda = lda;
     a.aligned = aligned16(A) && lda % 4 == 0;
     a.row_blocks = (int32_t)rb;
     a.col_strips = (int32_t)wstrips;
+    if (one_launch(v)) {
+        // one launch: the folds add into x1 (A y1) and x2 (A^T y2)
+        a.y1 = x1; a.y2 = x2;
+        a.aligned |= 2;
+        a.tag = next_tag(32);
+        return launch(v, 0, rb * strips, v->knobs[PK_K_THREADS], &a, sizeof a, s);
+    }
     PK_TRY(launch(v, 0, rb * strips, v->knobs[PK_K_THREADS], &a, sizeof a, s));
     const Variant *g = get_variant(ctx, ctx->def[PKF_GESUMMV]);
     pk_reduce_args r{};

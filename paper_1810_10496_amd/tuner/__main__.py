@@ -4,6 +4,8 @@
     python -m paper_1810_10496_amd.tuner gpu-filter  --workdir D      # execution-level pass filter (GPU)
     python -m paper_1810_10496_amd.tuner explore     --workdir D [--families a,b] [--samples 500]
     python -m paper_1810_10496_amd.tuner finalize    --workdir D [--families a,b]
+    python -m paper_1810_10496_amd.tuner refine      --workdir D [--families a,b] [--table path]
+                                                                      # one-launch grid into a finished table
     python -m paper_1810_10496_amd.tuner reuse       --workdir D
     python -m paper_1810_10496_amd.tuner table       --workdir D [--out path]
     python -m paper_1810_10496_amd.tuner report      --workdir D
@@ -28,7 +30,7 @@ def log(*a):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(prog="python -m paper_1810_10496_amd.tuner")
-    ap.add_argument("cmd", choices=["passes", "gpu-filter", "explore", "finalize", "reuse", "table", "report",
+    ap.add_argument("cmd", choices=["passes", "gpu-filter", "explore", "finalize", "refine", "reuse", "table", "report",
                                         "study", "phase", "orders-build", "orders-eval", "orders-finalize",
                                         "orders-minimise", "orders-permute", "orders-cross", "orders-table",
                                         "orders-report"])
@@ -104,6 +106,16 @@ def main(argv=None):
             for e in ents:
                 log(f"[finalize] {fam}/{e['size']}: speedup {e['speedup']:.3f} "
                     f"({'default' if e['is_default'] else e['pipeline'][:40]})")
+        return 0
+
+    if a.cmd == "refine":
+        from .. import tuned
+        path = a.table or tuned.TABLE
+        for fam in fams:
+            if fam not in X.ONE_LAUNCH_GRID:
+                continue
+            n = X.refine(fam, a.workdir, path, X.ONE_LAUNCH_GRID[fam], sizes, log=log, tag="one-launch grid")
+            log(f"[refine] {fam}: {n} entries replaced")
         return 0
 
     if a.cmd == "reuse":

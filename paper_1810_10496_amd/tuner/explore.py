@@ -310,6 +310,106 @@ def finalize(family, workdir, sizes=(256, 512, 1000, 2048, 4096), top=10, replay
     return entries
 
 
+# the one-launch forms (FUSE = 1) of the transposed matvec, the pair and the column
+# statistics: wavefronts stacked over the rows of one strip, the last block of each
+# group folding the partials; the grid `refine` adds to a table measured without them
+ONE_LAUNCH_GRID = {
+    "gemv_t": [dict(ROWS=r, WAVES=w, VEC=v, UNROLL=u, ORDER=0, FUSE=1) for r in (128, 256, 512)
+               for w in (4, 8) for v in (1, 2, 4) for u in (4, 8, 16)],
+    "gemv_pair": [dict(ROWS=r, WAVES=w, VEC=v, UNROLL=u, ORDER=0, FUSE=1) for r in (128, 256, 512)
+                  for w in (4, 8) for v in (1, 2, 4) for u in (4, 8, 16)],
+    "colstats": [dict(VEC=v, WAVES=w, ROWS=r, ORDER=0, FUSE=1) for v in (1, 2, 4) for w in (4, 8)
+                 for r in (128, 256, 512)],
+}
+
+
+def refine(family, workdir, table_path, grid, sizes=(256, 512, 1000, 2048, 4096), top=5, replays=30, seeds=30,
+           eval_timeout=300.0, log=print, margin=0.03, jobs=8, tag="refined"):
+    """Extend a finished table along new knob settings without a new exploration.
+
+    Every setting of `grid` (knob overrides of the family's default, -O3) is compiled,
+    gated, timed once per size; per size the `top` fastest, the table's current entry
+    and the default are re-timed with `replays` replays, and the fastest candidate
+    replaces the entry only if it beats the re-timed entry by `margin` and passes the
+    `seeds`-seed validation (as in finalize).  Entries are rewritten in `table_path`
+    in place; the default's time and the speedups are the re-timed ones."""
+    from .. import tuned
+    from ..api import Context
+    db = DB(os.path.join(workdir, "db.jsonl"))
+    variants = [space.Variant(family, dict(space.default_knobs(family), **g), codegen.DEFAULT_PIPELINE)
+                for g in grid]
+    variants = [v for v in variants if space.valid(family, v.knobs)]
+    recs = _build_many(db, variants, workdir, jobs)
+    cands = [(v, r) for v, r in zip(variants, recs) if r["status"] == "ok"]
+    log(f"[refine] {family}: {len(cands)} of {len(variants)} grid settings built and gated")
+    with open(table_path) as f:
+        doc = json.load(f)
+    entries = doc["entries"]
+    ev = Evaluator(family, sizes, log=log, stderr_path=os.path.join(workdir, f"worker_{family}.err"))
+    changed = 0
+    try:
+        for size in sizes:
+            key = str(size)
+            bucket = Context.size_bucket(size)
+            idx = [i for i, e in enumerate(entries) if e["family"] == family and int(e["bucket"]) == bucket]
+            if len(idx) != 1:
+                log(f"[refine] {family}/{size}: no single table entry, skipped")
+                continue
+            cur = entries[idx[0]]
+            once = []
+            for v, r in cands:
+                e = _evaluate(ev, db, family, r["sha"], _co_path(workdir, family, r["sha"]), [size], None,
+                              eval_timeout, validate=True, seeds=1)
+                if e["status"] == "ok" and key in e["times"]:
+                    once.append((e["times"][key], r["sha"], v))
+            once.sort(key=lambda t: t[0])
+            d = _evaluate(ev, db, family, "default", "default", [size], None, eval_timeout, replays=replays,
+                          validate=False)
+            t_def = d["times"].get(key, math.inf)
+            t_cur = t_def
+            if not cur.get("is_default"):
+                code = tuned.code_for(cur)
+                if code is None:
+                    log(f"[refine] {family}/{size}: the table entry does not reproduce, skipped")
+                    continue
+                p = _co_path(workdir, family, cur["code_sha256"])
+                os.makedirs(os.path.dirname(p), exist_ok=True)
+                with open(p, "wb") as f:
+                    f.write(code)
+                c = _evaluate(ev, db, family, cur["code_sha256"], p, [size], None, eval_timeout,
+                              replays=replays, validate=False)
+                t_cur = c["times"].get(key, math.inf)
+            timed = []
+            for _, sha, v in once[:top]:
+                e = _evaluate(ev, db, family, sha, _co_path(workdir, family, sha), [size], None, eval_timeout,
+                              replays=replays, validate=False)
+                if e["status"] == "ok" and key in e["times"]:
+                    timed.append((e["times"][key], sha, v))
+            timed.sort(key=lambda t: t[0])
+            log(f"[refine] {family}/{size}: default {t_def:.4f} ms, table {t_cur:.4f} ms, best of grid "
+                + (f"{timed[0][0]:.4f} ms {timed[0][2].knobs}" if timed else "-"))
+            if not timed or timed[0][0] >= t_cur * (1.0 - margin):
+                entries[idx[0]] = dict(cur, default_ms=t_def, tuned_ms=t_cur, speedup=t_def / t_cur)
+                continue
+            t, sha, v = timed[0]
+            val = _evaluate(ev, db, family, sha, _co_path(workdir, family, sha), [], None, eval_timeout,
+                            validate=True, seeds=seeds)
+            if val["status"] != "ok":
+                log(f"[refine] {family}/{size}: {sha[:10]} failed the {seeds}-seed validation")
+                continue
+            entries[idx[0]] = dict(family=family, bucket=bucket, size=size, is_default=False, knobs=v.knobs,
+                                   pipeline=v.pipeline, llc_flags=list(v.llc_flags), opt_flags=list(v.opt_flags),
+                                   code_sha256=sha, default_ms=t_def, tuned_ms=t, speedup=t_def / t,
+                                   source=tag)
+            changed += 1
+    finally:
+        ev.close()
+    doc["entries"] = entries
+    with open(table_path, "w") as f:
+        json.dump(doc, f, indent=1, sort_keys=True)
+    return changed
+
+
 def reuse(families, workdir, sizes=(256, 512, 1000, 2048, 4096), ks=(1, 3), trials=1000, replays=10,
           eval_timeout=300.0, jobs=8, log=print, seed=5500):
     """Feature-based reuse with leave-one-out, and the random-K control."""

@@ -27,14 +27,15 @@ DOMAINS = {
     "gemv": dict(ROWS=[1, 2, 4], WAVES=[1, 2, 4, 8], VEC=[1, 2, 4], UNROLL=[1, 2, 4, 8],
                  USE_LDS=[0, 1], ORDER=[0]),
     "gemv_t": dict(ROWS=[16, 32, 64, 128, 256], WAVES=[1, 2, 4, 8], VEC=[1, 2, 4], UNROLL=[1, 2, 4, 8, 16],
-                   ORDER=[0, 1]),
+                   ORDER=[0, 1], FUSE=[0, 1]),
     "gemv_pair": dict(ROWS=[16, 32, 64, 128, 256], WAVES=[1, 2, 4, 8], VEC=[1, 2, 4], UNROLL=[4, 8, 16, 32],
-                      ORDER=[0, 1]),
+                      ORDER=[0, 1], FUSE=[0, 1]),
     "conv2d": dict(VEC=[1, 2, 4], TX=[16, 32, 64, 128], TY=[1, 2, 4, 8, 16], ROWS=[1, 2, 4, 8, 16],
                    UNROLL=[1, 2, 4], USE_LDS=[0, 1], ORDER=[0, 1, 2]),
     "conv3d": dict(VEC=[1, 2, 4], TX=[16, 32, 64, 128], TY=[1, 2, 4, 8, 16], ROWS=[1, 2, 4, 8, 16, 32],
                    UNROLL=[1, 2], USE_LDS=[0, 1, 2], ORDER=[0, 1, 2], YR=[1, 2, 4, 8]),
-    "colstats": dict(VEC=[1, 2, 4], WAVES=[1, 2, 4, 8], ROWS=[16, 32, 64, 128, 256], ORDER=[0, 1]),
+    "colstats": dict(VEC=[1, 2, 4], WAVES=[1, 2, 4, 8], ROWS=[16, 32, 64, 128, 256], ORDER=[0, 1],
+                     FUSE=[0, 1]),
     "syrk_f32": dict(BT=[32, 48, 64, 96, 128], BK=[16, 32], WAVES_M=[1, 2, 4], WAVES_N=[1, 2, 4],
                      VEC=[1, 2, 4], STAGES=[1, 2], ORDER=[0, 2]),
 }
@@ -153,6 +154,11 @@ def valid(family: str, k: dict) -> bool:
     if family == "gemv":
         return True
     if family in ("gemv_t", "gemv_pair"):
+        if k.get("FUSE", 0):
+            # one launch: the wavefronts share the block's columns and split its rows
+            rpw = k["ROWS"] // k["WAVES"]
+            return (k["ROWS"] % k["WAVES"] == 0 and rpw % k["UNROLL"] == 0
+                    and k["UNROLL"] * k["VEC"] <= 128)
         return k["ROWS"] % k["UNROLL"] == 0 and k["UNROLL"] * k["VEC"] <= 128
     if family in ("conv2d", "conv3d"):
         nt = k["TX"] * k["TY"]

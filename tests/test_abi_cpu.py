@@ -57,18 +57,25 @@ def ws(kernel, dims, prec=0):
 def test_workspace_bounds():
     assert ws(0, [512, 512, 512]) == (0, 0)                           # gemm
     assert ws(1, [2048, 2048, 2048, 2048]) == (0, 2048 * 2048 * 4)   # gemm3: T
-    st, b = ws(3, [4096, 4096])                                       # gemv_t partials
-    assert st == 0 and b == (4096 // 16) * 4096 * 4
-    st, b2 = ws(4, [4096, 4096])                                      # pair: + y1 partials
-    assert st == 0 and b2 == b + (4096 // 64) * 4096 * 4
-    st, b = ws(8, [2048, 2048])                                       # corr: colstats partials
-    assert st == 0 and b == (2048 // 16) * 3 * 2048 * 4
+    a256 = lambda b: (b + 255) // 256 * 256                           # noqa: E731
+    ld = lambda n: (n + 63) // 64 * 64                                # noqa: E731  partial row stride
+    cell = 256                                                        # bytes per ticket cell
+    # gemv_t: partials of the smallest row blocks (16 rows), then one ticket cell per
+    # narrowest strip (64 columns)
+    st, b = ws(3, [4096, 4096])
+    assert st == 0 and b == a256((4096 // 16) * ld(4096) * 4) + (4096 // 64) * cell
+    st, b2 = ws(4, [4096, 4096])                                      # pair: + row-block cells, y1 partials
+    assert st == 0 and b2 == (a256((4096 // 16) * ld(4096) * 4) + (4096 // 64 + 4096 // 16) * cell
+                              + (4096 // 64) * 4096 * 4)
+    st, b = ws(3, [300, 70])
+    assert st == 0 and b == a256(19 * 128 * 4) + 2 * cell
+    st, b = ws(8, [2048, 2048])                                       # corr: colstats partials + cells
+    assert st == 0 and b == a256((2048 // 16) * 3 * ld(2048) * 4) + (2048 // 64) * cell
     assert ws(3, [-1, 4])[0] == 2                                     # negative -> SHAPE
     assert ws(42, [1, 1])[0] == 1                                     # bad kernel -> INVALID_ARG
     assert ws(1, [1, 1])[0] == 1                                      # too few dims
     assert ws(0, [1, 1, 1], prec=7)[0] == 1                           # bad precision
     # pk_sgemm_ws: bf16 one plane, split two, of A [M][Kp] and B^T [N][Kp], Kp = K up to 64
-    a256 = lambda b: (b + 255) // 256 * 256                           # noqa: E731
     assert ws(0, [300, 200, 129], prec=1) == (0, a256(300 * 192 * 2) + a256(200 * 192 * 2))
     assert ws(0, [300, 200, 129], prec=2) == (0, 2 * (a256(300 * 192 * 2) + a256(200 * 192 * 2)))
     assert ws(0, [5, 6, 0], prec=1) == (0, a256(5 * 64 * 2) + a256(6 * 64 * 2))    # K = 0 still pads
@@ -79,7 +86,7 @@ def test_workspace_bounds():
     p2 = a256(M * 128 * 2) + a256(N * 128 * 2)
     assert ws(1, [M, N, K, L], prec=1) == (0, t + max(p1, p2))
     # corr / covar in bf16 / split: + Z^T planes [m][n rounded up to 64]
-    part = (130 // 16 + 1) * 3 * 70 * 4
+    part = a256((130 // 16 + 1) * 3 * ld(70) * 4) + 2 * cell
     assert ws(8, [130, 70]) == (0, part)
     assert ws(8, [130, 70], prec=1) == (0, a256(part) + a256(70 * 192 * 2))
     assert ws(8, [130, 70], prec=2) == (0, a256(part) + 2 * a256(70 * 192 * 2))

@@ -5,7 +5,7 @@
     python -m paper_1810_10496_amd.tuner explore     --workdir D [--families a,b] [--samples 500]
     python -m paper_1810_10496_amd.tuner finalize    --workdir D [--families a,b]
     python -m paper_1810_10496_amd.tuner refine      --workdir D [--families a,b] [--table path]
-                                                                      # one-launch grid into a finished table
+                                                                      # a structured grid into a finished table
     python -m paper_1810_10496_amd.tuner reuse       --workdir D
     python -m paper_1810_10496_amd.tuner table       --workdir D [--out path]
     python -m paper_1810_10496_amd.tuner report      --workdir D
@@ -112,9 +112,10 @@ def main(argv=None):
         from .. import tuned
         path = a.table or tuned.TABLE
         for fam in fams:
-            if fam not in X.ONE_LAUNCH_GRID:
+            if fam not in X.REFINE_GRIDS:
                 continue
-            n = X.refine(fam, a.workdir, path, X.ONE_LAUNCH_GRID[fam], sizes, log=log, tag="one-launch grid")
+            tag = "one-launch grid" if fam in X.ONE_LAUNCH_GRID else "structured grid"
+            n = X.refine(fam, a.workdir, path, X.REFINE_GRIDS[fam], sizes, log=log, tag=tag, jobs=a.jobs)
             log(f"[refine] {fam}: {n} entries replaced")
         return 0
 

@@ -217,10 +217,15 @@ extern "C" __global__ void __launch_bounds__(NT) pk_conv2d(pk_conv2d_args a) {
 #ifndef YR
 #define YR 4
 #endif
+#ifndef PF          // planes fetched ahead into registers: 1, or 2 (two register tiles in turn)
+#define PF 1
+#endif
+static_assert(PF == 1 || PF == 2, "PF must be 1 or 2");
 constexpr int BYT = TY * YR;
 constexpr int LW4 = BX + 8;                 // tile row: halo at 3, interior at 4 .. BX+3, halo at BX+4
 constexpr int LP4 = (BYT + 2) * LW4;
-PK_DEFINE_KNOBS(PKF_CONV3D, BYT, BX, ROWS, TY, TX, VEC, UNROLL, 2, ORDER, YR, 0, NT, 4 * LP4 * 4,
+// knob slot X2 records PF when it is not 1
+PK_DEFINE_KNOBS(PKF_CONV3D, BYT, BX, ROWS, TY, TX, VEC, UNROLL, 2, ORDER, YR, (PF == 1 ? 0 : PF), NT, 4 * LP4 * 4,
                 PK_KERNEL_ABI_VERSION, 0)
 #else
 // LDS variant: a ring of three haloed (TY+2) x (BX+2) plane tiles
@@ -477,6 +482,69 @@ template <int CV> struct PlaneTile {
     }
 };
 
+#if PF == 2
+// output plane z (step r: its input planes z-1, z, z+1 sit in ring slots r, r+1, r+2
+// mod 4): each thread's VEC x YR patch from the 27 taps, then stored
+template <int CV>
+__device__ __forceinline__ void staged_plane(const pk_conv3d_args &a, const float *ring, int r, int64_t z,
+                                             int64_t x0, int64_t y0, int tx, int ty, const float *w) {
+    if (x0 >= a.W || y0 >= a.H)
+        return;
+    float acc[YR][VEC];
+#pragma unroll
+    for (int i = 0; i < YR; ++i)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+            acc[i][e] = 0.f;
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz) {
+        const float *pl = ring + ((r + dz) % 4) * LP4 + 3 + tx * VEC;
+#pragma unroll
+        for (int rr = 0; rr < YR + 2; ++rr) {              // tile row ty*YR + rr = output row y0 + rr - 1
+            float v[VEC + 2];
+#pragma unroll
+            for (int d = 0; d < VEC + 2; ++d)
+                v[d] = pl[(ty * YR + rr) * LW4 + d];
+#pragma unroll
+            for (int i = 0; i < YR; ++i) {
+                const int dy = rr - i;                      // input row y0+i-1+dy
+                if (dy < 0 || dy > 2)
+                    continue;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e)
+#pragma unroll
+                    for (int dx = 0; dx < 3; ++dx)
+                        acc[i][e] += w[dz * 9 + dy * 3 + dx] * v[e + dx];
+            }
+        }
+    }
+    const bool zb = (z == 0 || z == a.D - 1);
+#pragma unroll
+    for (int i = 0; i < YR; ++i) {
+        const int64_t y = y0 + i;
+        if (y >= a.H)
+            break;
+        float o[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const int64_t x = x0 + e;
+            o[e] = (zb || y == 0 || y == a.H - 1 || x == 0 || x >= a.W - 1) ? 0.f : acc[i][e];
+        }
+        float *orow = a.out + (z * a.H + y) * a.W;
+        if (CV > 1 && x0 + VEC <= a.W) {
+#pragma unroll
+            for (int e = 0; e < VEC; e += (VEC < CV ? VEC : CV))
+                pk_stv<(VEC < CV ? VEC : CV)>(orow + x0 + e, o + e);
+        } else {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+                if (x0 + e < a.W)
+                    orow[x0 + e] = o[e];
+        }
+    }
+}
+#endif
+
 template <int CV>
 __device__ __forceinline__ void conv3d_staged_body(const pk_conv3d_args &a, float *ring) {
     const int tx = threadIdx.x % TX;
@@ -505,6 +573,38 @@ __device__ __forceinline__ void conv3d_staged_body(const pk_conv3d_args &a, floa
     for (int t = 0; t < 27; ++t)
         w[t] = a.w[t];
 
+#if PF == 2
+    // two register tiles in turn: the loads for plane z0 + r + 4 are issued during
+    // step r and stored to LDS at the end of step r + 2, so two planes' arithmetic
+    // covers each plane's load latency (slot k % 4 holds plane z0 - 1 + k as below)
+    PlaneTile<CV> pa, pb;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        pa.load(a, z0 - 1 + k, gy0, gx0);
+        pa.store(ring + k * LP4);
+    }
+    __syncthreads();
+    pa.load(a, z0 + 2, gy0, gx0);
+    pb.load(a, z0 + 3, gy0, gx0);
+    for (int r = 0; r < ROWS; r += 2) {
+        if (z0 + r >= a.D)
+            break;                                          // uniform across the block
+        staged_plane<CV>(a, ring, r, z0 + r, x0, y0, tx, ty, w);
+        if (r + 1 < ROWS)
+            pa.store(ring + ((r + 3) % 4) * LP4);           // plane z0 + r + 2
+        __syncthreads();
+        if (r + 3 < ROWS)
+            pa.load(a, z0 + r + 4, gy0, gx0);
+        if (r + 1 >= ROWS || z0 + r + 1 >= a.D)
+            break;
+        staged_plane<CV>(a, ring, r + 1, z0 + r + 1, x0, y0, tx, ty, w);
+        if (r + 2 < ROWS)
+            pb.store(ring + ((r + 4) % 4) * LP4);           // plane z0 + r + 3
+        __syncthreads();
+        if (r + 4 < ROWS)
+            pb.load(a, z0 + r + 5, gy0, gx0);
+    }
+#else
     // slot k % 4 holds plane z0 - 1 + k
     PlaneTile<CV> pt;
 #pragma unroll
@@ -578,6 +678,7 @@ __device__ __forceinline__ void conv3d_staged_body(const pk_conv3d_args &a, floa
         if (r + 2 < ROWS)
             pt.load(a, z0 + r + 3, gy0, gx0);
     }
+#endif
 }
 #endif
 

@@ -326,14 +326,17 @@ ONE_LAUNCH_GRID = {
 def _stencil_grids():
     """Structured grids around the stencils' best sampled variants: the 3D stencil's
     staged form with tiles 128 or 256 columns wide (256 = a whole row of the 256^3
-    volume: no x halo), 16 or 32 rows and 8-32 planes per block; the 2D stencil's
+    volume: no x halo), 16 or 32 rows, 8-32 planes per block and one or two planes
+    fetched ahead; the 2D stencil's
     register-window form with 256-1024-column tiles."""
     g3 = []
     for tx, vec in ((32, 4), (64, 2), (64, 4), (128, 1), (128, 2)):
         for ty, yr in ((2, 8), (4, 4), (8, 2), (4, 8), (8, 4)):
             for rows in (8, 16, 32):
                 for order in (0, 1, 2):
-                    g3.append(dict(TX=tx, VEC=vec, TY=ty, YR=yr, ROWS=rows, USE_LDS=2, UNROLL=1, ORDER=order))
+                    for pf in (1, 2):
+                        g3.append(dict(TX=tx, VEC=vec, TY=ty, YR=yr, ROWS=rows, USE_LDS=2, UNROLL=1, ORDER=order,
+                                       PF=pf))
     g2 = [dict(TX=tx, VEC=vec, TY=ty, ROWS=rows, UNROLL=1, USE_LDS=0, ORDER=order)
           for tx in (64, 128, 256) for vec in (2, 4) for ty in (1, 2, 4) for rows in (8, 16, 32)
           for order in (0, 2)]

@@ -113,6 +113,10 @@ VARIANTS = [
     ("conv3d", dict(VEC=4, TX=64, TY=4, ROWS=8, USE_LDS=2, YR=4, ORDER=0), "default<O3>"),
     ("conv3d", dict(VEC=2, TX=16, TY=8, ROWS=4, USE_LDS=2, YR=2, ORDER=2), "default<O3>"),
     ("conv3d", dict(VEC=1, TX=32, TY=2, ROWS=32, USE_LDS=2, YR=8, ORDER=1), "default<O3>"),
+    # ... with two planes fetched ahead (two register tiles in turn), including one plane per block
+    ("conv3d", dict(VEC=1, TX=128, TY=4, ROWS=8, USE_LDS=2, YR=8, ORDER=1, PF=2), "default<O3>"),
+    ("conv3d", dict(VEC=4, TX=64, TY=4, ROWS=1, USE_LDS=2, YR=4, ORDER=0, PF=2), "default<O3>"),
+    ("conv3d", dict(VEC=2, TX=32, TY=8, ROWS=32, USE_LDS=2, YR=2, ORDER=2, PF=2), "default<O3>"),
 ]
 
 

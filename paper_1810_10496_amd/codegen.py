@@ -84,10 +84,10 @@ FAMILIES = {f.name: f for f in [
     _fs("gesummv", 14, "gesummv.hip", {}, dict(ROWS=1, WAVES=4, VEC=4, UNROLL=4), "gesummv"),
     _fs("fdtd", 15, "fdtd.hip", {}, dict(VEC=4, TX=64, TY=4), "fdtd2d"),
     _fs("gemm_bf16_ws", 16, "gemm_bf.hip", {"PREC": 1},
-        dict(BM=256, BN=256, BK=64, WAVES_M=4, WAVES_N=4, ORDER=3, LDS_PAD=8, PIPE=1, DSTAGES=2, SCHED=1),
+        dict(BM=256, BN=256, BK=64, WAVES_M=4, WAVES_N=4, ORDER=3, LDS_PAD=8, PIPE=1, DSTAGES=2, SCHED=1, EPI=0),
         "gemm", "bf16"),
     _fs("gemm_split_ws", 17, "gemm_bf.hip", {"PREC": 2},
-        dict(BM=256, BN=256, BK=32, WAVES_M=4, WAVES_N=4, ORDER=3, LDS_PAD=8, PIPE=1, DSTAGES=2, SCHED=0),
+        dict(BM=256, BN=256, BK=32, WAVES_M=4, WAVES_N=4, ORDER=3, LDS_PAD=8, PIPE=1, DSTAGES=2, SCHED=0, EPI=0),
         "gemm", "split"),
     _fs("stream", 18, "stream.hip", {}, dict(NTHREADS=256, UNROLL=4), "stream"),
 ]}

@@ -68,6 +68,10 @@
 #ifndef SYRK         // 1: the correlation / covariance rank-k form (below)
 #define SYRK 0
 #endif
+#ifndef EPI          // 1: the epilogue can also write the result as the next product's prepared
+#define EPI 0        // operand (bf16 rows, hi and lo planes for split): chained products
+#endif
+static_assert(EPI == 0 || !SYRK, "EPI applies to the GEMM form");
 
 #if SYRK
 #define FAMILY ((PREC) == 1 ? PKF_SYRK_BF16 : PKF_SYRK_SPLIT)
@@ -117,7 +121,8 @@ static_assert(!SYRK || (BM == BN && (ORDER == 0 || ORDER == 2)), "rank-k form: s
 constexpr int PT = 64;    // transposing preparation: source columns per block
 constexpr int PTK = 64;   // ... and source rows per block (recorded in the knob record)
 
-PK_DEFINE_KNOBS(FAMILY, BM, BN, BK, WAVES_M, WAVES_N, 8, 1, 2, ORDER, PREC, 2, NT, LDS_TOTAL * 2,
+// knob slot X2: 2, or 3 when the epilogue can write the prepared-operand layout (EPI)
+PK_DEFINE_KNOBS(FAMILY, BM, BN, BK, WAVES_M, WAVES_N, 8, 1, 2, ORDER, PREC, 2 + EPI, NT, LDS_TOTAL * 2,
                 PK_KERNEL_ABI_VERSION, PTK)
 
 __device__ __forceinline__ void tile_of(int bid, int tiles_m, int tiles_n, int &tm, int &tn) {
@@ -693,6 +698,35 @@ extern "C" __global__ void __launch_bounds__(NT) pk_gemm_bf(pk_gemmbf_args a) {
             }
         }
 #else
+#if EPI
+    if (a.ldd < 0) {
+        // the result as the next product's prepared operand: rows of -ldd bf16 values
+        // (a multiple of 64 covered by the tile columns), RNE hi and, for split, lo =
+        // bf16(v - hi) one plane of M rows further; zeros beyond column N
+        const int64_t ldt = -a.ldd;
+        uint16_t *th = reinterpret_cast<uint16_t *>(a.D);
+        uint16_t *tl = th + a.M * ldt;
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const int64_t col = col0 + wn * WTN + j * 16 + l16;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = row0 + wm * WTM + i * 16 + 4 * g + r;
+                    if (row < a.M && col < ldt) {
+                        const float v = col < a.N ? a.alpha * acc[i][j][r] : 0.f;
+                        uint32_t hb, lb;
+                        pk_split(v, hb, lb);
+                        th[row * ldt + col] = (uint16_t)hb;
+                        if (PLANES == 2)
+                            tl[row * ldt + col] = (uint16_t)lb;
+                    }
+                }
+            }
+        return;
+    }
+#endif
     const bool use_c = a.beta != 0.f;
 #pragma unroll
     for (int i = 0; i < FM; ++i)

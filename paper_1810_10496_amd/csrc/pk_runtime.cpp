@@ -429,13 +429,28 @@ pk_status run_gemm(pk_context *ctx, int family, int64_t M, int64_t N, int64_t K,
 }
 
 size_t ws_gemm_bf(pk_precision prec, int64_t M, int64_t N, int64_t K);
+int64_t prep_kp(int64_t K);
 // chained product: T (M x L, FP32), then for bf16 / split the larger of the two
 // products' prepared operands
-size_t ws_gemm3(pk_precision prec, int64_t M, int64_t N, int64_t K, int64_t L) {
+size_t ws_gemm3_t(pk_precision prec, int64_t M, int64_t N, int64_t K, int64_t L) {
     const size_t t = (size_t)M * (size_t)L * 4;
     if (prec == PK_FP32)
         return t;
     return align256(t) + std::max(ws_gemm_bf(prec, M, L, K), ws_gemm_bf(prec, M, N, L));
+}
+// bf16 / split with T written straight as the second product's prepared A operand:
+// T's planes (M rows of Kp2 = L rounded up to 64, hi then lo), then the larger of the
+// first product's prepared operands and the second product's prepared C^T
+size_t ws_gemm3_direct(pk_precision prec, int64_t M, int64_t N, int64_t K, int64_t L) {
+    const size_t planes = prec == PK_SPLIT_BF16 ? 2 : 1;
+    const size_t kp2 = (size_t)prep_kp(L);
+    return align256(planes * (size_t)M * kp2 * 2) +
+           std::max(ws_gemm_bf(prec, M, L, K), planes * align256((size_t)N * kp2 * 2));
+}
+size_t ws_gemm3(pk_precision prec, int64_t M, int64_t N, int64_t K, int64_t L) {
+    if (prec == PK_FP32)
+        return ws_gemm3_t(prec, M, N, K, L);
+    return std::max(ws_gemm3_t(prec, M, N, K, L), ws_gemm3_direct(prec, M, N, K, L));
 }
 
 int gemm_family(pk_precision p) {
@@ -455,25 +470,46 @@ size_t ws_gemm_bf(pk_precision prec, int64_t M, int64_t N, int64_t K) {
     return planes * (align256((size_t)M * kp * 2) + align256((size_t)N * kp * 2));
 }
 
+// D = alpha A B + beta C from operands prepared in `ws` (A as [M][Kp], B^T as [N][Kp]).
+// With `pre_h` (and `pre_l` for split) A is already prepared there ([M][Kp] rows, as the
+// preparation writes them) and only B^T is prepared, at the start of `ws`.  With `out_t`
+// the result is not stored to D but written as the next product's prepared A operand:
+// M rows of `out_kp` bf16 values (the hi plane, then for split the lo plane right
+// after it), which the variant must support (knob slot X2 = 3).
 pk_status run_gemm_bf(pk_context *ctx, pk_precision prec, int64_t M, int64_t N, int64_t K, float alpha,
                       const float *A, int64_t lda, const float *B, int64_t ldb, float beta, const float *C,
-                      int64_t ldc, float *D, int64_t ldd, void *ws, hipStream_t s) {
+                      int64_t ldc, float *D, int64_t ldd, void *ws, hipStream_t s,
+                      const uint16_t *pre_h = nullptr, const uint16_t *pre_l = nullptr,
+                      uint16_t *out_t = nullptr, int64_t out_kp = 0) {
     const int family = prec == PK_BF16 ? PKF_GEMM_BF16_WS : PKF_GEMM_SPLIT_WS;
     const Variant *v = pick(ctx, family, std::max(M, std::max(N, K)));
     if (!v)
         return fail(PK_ERR_NO_VARIANT, "no variant for family %d", family);
+    if (out_t && v->knobs[PK_K_X2] != 3)
+        return fail(PK_ERR_NO_VARIANT, "variant cannot write a prepared operand");
     const bool split = prec == PK_SPLIT_BF16;
     const int64_t kp = prep_kp(K);
     char *w = static_cast<char *>(ws);
     const size_t a_pl = align256((size_t)M * (size_t)kp * 2), b_pl = align256((size_t)N * (size_t)kp * 2);
-    uint16_t *Ah = reinterpret_cast<uint16_t *>(w);
-    uint16_t *Al = split ? reinterpret_cast<uint16_t *>(w + a_pl) : nullptr;
-    uint16_t *Bh = reinterpret_cast<uint16_t *>(w + (split ? 2 : 1) * a_pl);
-    uint16_t *Bl = split ? reinterpret_cast<uint16_t *>(w + 2 * a_pl + b_pl) : nullptr;
-    pk_gemmprep_args pa{};
-    pa.src = A; pa.hi = Ah; pa.lo = Al; pa.rows = M; pa.cols = K; pa.ld = std::max<int64_t>(lda, 1);
-    pa.ldo = kp; pa.transpose = 0; pa.split = split ? 1 : 0;
-    PK_TRY(launch(v, 1, std::min<int64_t>(cdiv(M * (kp / 8), 256), 16384), 256, &pa, sizeof pa, s));
+    const uint16_t *Ah, *Al;
+    uint16_t *Bh, *Bl;
+    if (pre_h) {
+        Ah = pre_h;
+        Al = split ? pre_l : nullptr;
+        Bh = reinterpret_cast<uint16_t *>(w);
+        Bl = split ? reinterpret_cast<uint16_t *>(w + b_pl) : nullptr;
+    } else {
+        uint16_t *ah = reinterpret_cast<uint16_t *>(w);
+        uint16_t *al = split ? reinterpret_cast<uint16_t *>(w + a_pl) : nullptr;
+        Ah = ah;
+        Al = al;
+        Bh = reinterpret_cast<uint16_t *>(w + (split ? 2 : 1) * a_pl);
+        Bl = split ? reinterpret_cast<uint16_t *>(w + 2 * a_pl + b_pl) : nullptr;
+        pk_gemmprep_args pa{};
+        pa.src = A; pa.hi = ah; pa.lo = al; pa.rows = M; pa.cols = K; pa.ld = std::max<int64_t>(lda, 1);
+        pa.ldo = kp; pa.transpose = 0; pa.split = split ? 1 : 0;
+        PK_TRY(launch(v, 1, std::min<int64_t>(cdiv(M * (kp / 8), 256), 16384), 256, &pa, sizeof pa, s));
+    }
     pk_gemmprep_args pb{};
     pb.src = B; pb.hi = Bh; pb.lo = Bl; pb.rows = K; pb.cols = N; pb.ld = ldb;
     pb.ldo = kp; pb.transpose = 1; pb.split = split ? 1 : 0;
@@ -481,6 +517,11 @@ pk_status run_gemm_bf(pk_context *ctx, pk_precision prec, int64_t M, int64_t N, 
     pk_gemmbf_args a{};
     a.Ah = Ah; a.Al = Al; a.Bh = Bh; a.Bl = Bl; a.C = C; a.D = D;
     a.M = M; a.N = N; a.Kp = kp; a.ldc = ldc; a.ldd = ldd; a.alpha = alpha; a.beta = beta;
+    if (out_t) {
+        a.C = nullptr; a.beta = 0.f;
+        a.D = reinterpret_cast<float *>(out_t);
+        a.ldd = -out_kp;                                   // the prepared-operand epilogue
+    }
     const int64_t grid = cdiv(M, v->knobs[PK_K_TM]) * cdiv(N, v->knobs[PK_K_TN]);
     return launch(v, 0, grid, v->knobs[PK_K_THREADS], &a, sizeof a, s);
 }
@@ -841,7 +882,15 @@ pk_status pk_sgemm3(pk_context *ctx, pk_precision prec, int64_t M, int64_t N, in
         return fail(PK_ERR_SHAPE, "leading dimension smaller than the row length");
     if (M == 0 || N == 0)
         return PK_OK;
-    const size_t need = ws_gemm3(prec, M, N, K, L);
+    // bf16 / split: T goes straight into the second product's prepared operand when the
+    // first product's variant can write that layout (the preparation pass of T is saved)
+    bool direct = false;
+    if (prec != PK_FP32 && L > 0) {
+        const Variant *v1 = pick(ctx, prec == PK_BF16 ? PKF_GEMM_BF16_WS : PKF_GEMM_SPLIT_WS,
+                                 std::max(M, std::max(L, K)));
+        direct = v1 && v1->knobs[PK_K_X2] == 3 && v1->knobs[PK_K_TN] % 64 == 0;   // tiles cover Kp2
+    }
+    const size_t need = direct ? ws_gemm3_direct(prec, M, N, K, L) : ws_gemm3_t(prec, M, N, K, L);
     if (ws_bytes < need)
         return fail(PK_ERR_INVALID_ARG, "workspace too small: %zu < %zu bytes", ws_bytes, need);
     PK_TRY(check_ptr(ctx, A, mat_bytes(M, K, lda), "A"));
@@ -851,6 +900,18 @@ pk_status pk_sgemm3(pk_context *ctx, pk_precision prec, int64_t M, int64_t N, in
     PK_TRY(check_ptr(ctx, ws, need, "workspace"));
     float *T = static_cast<float *>(ws);
     hipStream_t s = (hipStream_t)stream;
+    if (direct) {
+        if (reinterpret_cast<uintptr_t>(ws) & 255u)
+            return fail(PK_ERR_ALIGNMENT, "workspace must be 256-byte aligned");
+        const bool split = prec == PK_SPLIT_BF16;
+        const int64_t kp2 = prep_kp(L);
+        uint16_t *th = static_cast<uint16_t *>(ws);
+        uint16_t *tl = split ? th + M * kp2 : nullptr;
+        void *rest = static_cast<char *>(ws) + align256((split ? 2 : 1) * (size_t)M * (size_t)kp2 * 2);
+        PK_TRY(run_gemm_bf(ctx, prec, M, L, K, 1.0f, A, lda, B, ldb, 0.0f, nullptr, L, nullptr, L, rest, s,
+                           nullptr, nullptr, th, kp2));
+        return run_gemm_bf(ctx, prec, M, N, L, alpha, nullptr, 0, Cm, ldcm, beta, D, ldd, D, ldd, rest, s, th, tl);
+    }
     if (prec != PK_FP32) {
         if (reinterpret_cast<uintptr_t>(ws) & 255u)
             return fail(PK_ERR_ALIGNMENT, "workspace must be 256-byte aligned");

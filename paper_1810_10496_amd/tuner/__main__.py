@@ -6,6 +6,8 @@
     python -m paper_1810_10496_amd.tuner finalize    --workdir D [--families a,b]
     python -m paper_1810_10496_amd.tuner refine      --workdir D [--families a,b] [--table path]
                                                                       # a structured grid into a finished table
+    python -m paper_1810_10496_amd.tuner upgrade     --workdir D --families gemm_bf16_ws,gemm_split_ws
+                                                                      # entries rebuilt with the EPI epilogue
     python -m paper_1810_10496_amd.tuner reuse       --workdir D
     python -m paper_1810_10496_amd.tuner table       --workdir D [--out path]
     python -m paper_1810_10496_amd.tuner report      --workdir D
@@ -30,7 +32,7 @@ def log(*a):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(prog="python -m paper_1810_10496_amd.tuner")
-    ap.add_argument("cmd", choices=["passes", "gpu-filter", "explore", "finalize", "refine", "reuse", "table", "report",
+    ap.add_argument("cmd", choices=["passes", "gpu-filter", "explore", "finalize", "refine", "upgrade", "reuse", "table", "report",
                                         "study", "phase", "orders-build", "orders-eval", "orders-finalize",
                                         "orders-minimise", "orders-permute", "orders-cross", "orders-table",
                                         "orders-report"])
@@ -117,6 +119,17 @@ def main(argv=None):
             tag = "one-launch grid" if fam in X.ONE_LAUNCH_GRID else "structured grid"
             n = X.refine(fam, a.workdir, path, X.REFINE_GRIDS[fam], sizes, log=log, tag=tag, jobs=a.jobs)
             log(f"[refine] {fam}: {n} entries replaced")
+        return 0
+
+    if a.cmd == "upgrade":
+        # the prepared bf16 / split GEMM entries gain the prepared-operand epilogue (EPI),
+        # which the chained product uses to write T straight into its second product
+        from .. import tuned
+        path = a.table or tuned.TABLE
+        for fam in fams:
+            if fam in ("gemm_bf16_ws", "gemm_split_ws"):
+                n = X.upgrade(fam, a.workdir, path, dict(EPI=1), sizes, log=log, tag="EPI upgrade", jobs=a.jobs)
+                log(f"[upgrade] {fam}: {n} entries upgraded")
         return 0
 
     if a.cmd == "reuse":

@@ -433,6 +433,63 @@ def refine(family, workdir, table_path, grid, sizes=(256, 512, 1000, 2048, 4096)
     return changed
 
 
+def upgrade(family, workdir, table_path, extra, sizes=(256, 512, 1000, 2048, 4096), replays=30, seeds=30,
+            eval_timeout=300.0, log=print, margin=0.03, jobs=8, tag="upgraded"):
+    """Rebuild each non-default table entry with the knobs `extra` added (a capability
+    that leaves the entry's own launches unchanged, e.g. EPI) and take the rebuilt code
+    object if, re-timed with `replays` replays beside the entry, it is not slower than
+    the entry by more than `margin` and it passes the `seeds`-seed validation."""
+    from .. import tuned
+    from ..api import Context
+    db = DB(os.path.join(workdir, "db.jsonl"))
+    with open(table_path) as f:
+        doc = json.load(f)
+    entries = doc["entries"]
+    ev = Evaluator(family, sizes, log=log, stderr_path=os.path.join(workdir, f"worker_{family}.err"))
+    changed = 0
+    try:
+        for size in sizes:
+            key = str(size)
+            bucket = Context.size_bucket(size)
+            idx = [i for i, e in enumerate(entries) if e["family"] == family and int(e["bucket"]) == bucket]
+            if len(idx) != 1 or entries[idx[0]].get("is_default"):
+                continue
+            cur = entries[idx[0]]
+            v = space.Variant(family, dict(cur["knobs"], **extra), cur["pipeline"],
+                              tuple(cur.get("llc_flags", ["-O3"])), tuple(cur.get("opt_flags", [])))
+            rec = _build_many(db, [v], workdir, jobs)[0]
+            code = tuned.code_for(cur)
+            if rec["status"] != "ok" or code is None:
+                log(f"[upgrade] {family}/{size}: not built ({rec['status']}) or the entry does not reproduce")
+                continue
+            p = _co_path(workdir, family, cur["code_sha256"])
+            os.makedirs(os.path.dirname(p), exist_ok=True)
+            with open(p, "wb") as f:
+                f.write(code)
+            c = _evaluate(ev, db, family, cur["code_sha256"], p, [size], None, eval_timeout, replays=replays,
+                          validate=False)
+            n = _evaluate(ev, db, family, rec["sha"], _co_path(workdir, family, rec["sha"]), [size], None,
+                          eval_timeout, replays=replays, validate=False)
+            t_cur, t_new = c["times"].get(key, math.inf), n["times"].get(key, math.inf)
+            log(f"[upgrade] {family}/{size}: entry {t_cur:.4f} ms, with {extra} {t_new:.4f} ms")
+            if not t_new <= t_cur * (1.0 + margin):
+                continue
+            val = _evaluate(ev, db, family, rec["sha"], _co_path(workdir, family, rec["sha"]), [], None,
+                            eval_timeout, validate=True, seeds=seeds)
+            if val["status"] != "ok":
+                log(f"[upgrade] {family}/{size}: failed the {seeds}-seed validation")
+                continue
+            entries[idx[0]] = dict(cur, knobs=v.knobs, code_sha256=rec["sha"], tuned_ms=t_new,
+                                   speedup=cur["default_ms"] / t_new, source=tag)
+            changed += 1
+    finally:
+        ev.close()
+    doc["entries"] = entries
+    with open(table_path, "w") as f:
+        json.dump(doc, f, indent=1, sort_keys=True)
+    return changed
+
+
 def reuse(families, workdir, sizes=(256, 512, 1000, 2048, 4096), ks=(1, 3), trials=1000, replays=10,
           eval_timeout=300.0, jobs=8, log=print, seed=5500):
     """Feature-based reuse with leave-one-out, and the random-K control."""

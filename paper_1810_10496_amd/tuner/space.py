@@ -27,18 +27,32 @@ DOMAINS = {
     "gemv": dict(ROWS=[1, 2, 4], WAVES=[1, 2, 4, 8], VEC=[1, 2, 4], UNROLL=[1, 2, 4, 8],
                  USE_LDS=[0, 1], ORDER=[0]),
     "gemv_t": dict(ROWS=[16, 32, 64, 128, 256], WAVES=[1, 2, 4, 8], VEC=[1, 2, 4], UNROLL=[1, 2, 4, 8, 16],
-                   ORDER=[0, 1], FUSE=[0, 1]),
+                   ORDER=[0, 1]),
     "gemv_pair": dict(ROWS=[16, 32, 64, 128, 256], WAVES=[1, 2, 4, 8], VEC=[1, 2, 4], UNROLL=[4, 8, 16, 32],
-                      ORDER=[0, 1], FUSE=[0, 1]),
+                      ORDER=[0, 1]),
     "conv2d": dict(VEC=[1, 2, 4], TX=[16, 32, 64, 128], TY=[1, 2, 4, 8, 16], ROWS=[1, 2, 4, 8, 16],
                    UNROLL=[1, 2, 4], USE_LDS=[0, 1], ORDER=[0, 1, 2]),
     "conv3d": dict(VEC=[1, 2, 4], TX=[16, 32, 64, 128], TY=[1, 2, 4, 8, 16], ROWS=[1, 2, 4, 8, 16, 32],
                    UNROLL=[1, 2], USE_LDS=[0, 1, 2], ORDER=[0, 1, 2], YR=[1, 2, 4, 8]),
-    "colstats": dict(VEC=[1, 2, 4], WAVES=[1, 2, 4, 8], ROWS=[16, 32, 64, 128, 256], ORDER=[0, 1],
-                     FUSE=[0, 1]),
+    "colstats": dict(VEC=[1, 2, 4], WAVES=[1, 2, 4, 8], ROWS=[16, 32, 64, 128, 256], ORDER=[0, 1]),
     "syrk_f32": dict(BT=[32, 48, 64, 96, 128], BK=[16, 32], WAVES_M=[1, 2, 4], WAVES_N=[1, 2, 4],
                      VEC=[1, 2, 4], STAGES=[1, 2], ORDER=[0, 2]),
 }
+# Knobs the kernels gained after the exploration sample was drawn: the random sample
+# leaves them at their defaults (so it, and the table measured from it, stay as they
+# were); `tuner refine` times structured grids over them against the finished table.
+#   FUSE: one launch for the transposed matvec, the pair and the column statistics
+#   PF:   planes fetched ahead by the staged 3D stencil
+#   EPI:  the prepared bf16 GEMM's epilogue can write the next product's prepared operand
+REFINE_ONLY = {
+    "gemv_t": dict(FUSE=[0, 1]),
+    "gemv_pair": dict(FUSE=[0, 1]),
+    "colstats": dict(FUSE=[0, 1]),
+    "conv3d": dict(PF=[1, 2]),
+    "gemm_bf16_ws": dict(EPI=[0, 1]),
+    "gemm_split_ws": dict(EPI=[0, 1]),
+}
+
 # the reduced-precision contractions: bf16 fragments need BK in multiples of 32
 for _fam in ("gemm_bf16", "gemm_split"):
     DOMAINS[_fam] = dict(BM=[64, 128, 256], BN=[64, 128, 256], BK=[32, 64], WAVES_M=[1, 2, 4], WAVES_N=[1, 2, 4],

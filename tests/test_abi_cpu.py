@@ -85,6 +85,16 @@ def test_workspace_bounds():
     p1 = a256(M * 192 * 2) + a256(L * 192 * 2)
     p2 = a256(M * 128 * 2) + a256(N * 128 * 2)
     assert ws(1, [M, N, K, L], prec=1) == (0, t + max(p1, p2))
+    # ... or, when the first product writes T straight into the second's prepared operand,
+    # T's bf16 planes ([M][L up to 64]) and the larger of the first product's operands and
+    # the second's C^T: whichever is larger (here L = 1, the direct layout)
+    L = 1
+    old = a256(M * L * 4) + max(a256(M * 192 * 2) + a256(L * 192 * 2), a256(M * 64 * 2) + a256(N * 64 * 2))
+    direct = a256(M * 64 * 2) + max(a256(M * 192 * 2) + a256(L * 192 * 2), a256(N * 64 * 2))
+    assert direct > old and ws(1, [M, N, K, L], prec=1) == (0, direct)
+    direct2 = a256(2 * M * 64 * 2) + max(2 * (a256(M * 192 * 2) + a256(L * 192 * 2)), 2 * a256(N * 64 * 2))
+    old2 = a256(M * L * 4) + 2 * max(a256(M * 192 * 2) + a256(L * 192 * 2), a256(M * 64 * 2) + a256(N * 64 * 2))
+    assert ws(1, [M, N, K, L], prec=2) == (0, max(direct2, old2))
     # corr / covar in bf16 / split: + Z^T planes [m][n rounded up to 64]
     part = a256((130 // 16 + 1) * 3 * ld(70) * 4) + 2 * cell
     assert ws(8, [130, 70]) == (0, part)

@@ -21,9 +21,10 @@ def test_defaults_are_valid_and_inside_the_domains():
     for fam in FAMS:
         k = space.default_knobs(fam)
         assert space.valid(fam, k), fam
+        extra = space.REFINE_ONLY.get(fam, {})
         for name, v in k.items():
-            assert v in space.DOMAINS[fam][name], (fam, name, v)
-        assert set(k) == set(space.DOMAINS[fam])
+            assert v in (extra[name] if name in extra else space.DOMAINS[fam][name]), (fam, name, v)
+        assert set(k) == set(space.DOMAINS[fam]) | set(extra)
 
 
 def test_sampling_is_seeded_valid_and_pipelines_shared():

@@ -176,8 +176,11 @@ pk_status pk_sgemm_ws(pk_context *ctx, pk_precision prec, int64_t M, int64_t N, 
  * M x K, B K x L, Cm L x N, D M x N.  T = A B is formed first, as FP32, in the
  * workspace (M*L floats); alpha is applied once, in the second product.  For
  * BF16 / SPLIT_BF16 both products run as in pk_sgemm_ws (T is rounded, or
- * re-split, when it is prepared for the second product) and the workspace
- * (pk_workspace_bytes(PK_KERNEL_GEMM3, ...)) must be 256-byte aligned. */
+ * re-split, for the second product: by the first product's epilogue straight into
+ * the second's prepared operand when the selected variant can, else by a separate
+ * preparation of the FP32 T; the results are the same bit for bit) and the
+ * workspace (pk_workspace_bytes(PK_KERNEL_GEMM3, ...), which covers both) must be
+ * 256-byte aligned. */
 pk_status pk_sgemm3(pk_context *ctx, pk_precision prec, int64_t M, int64_t N, int64_t K,
                     int64_t L, float alpha, const float *A, int64_t lda, const float *B,
                     int64_t ldb, const float *Cm, int64_t ldcm, float beta, float *D,
@@ -189,11 +192,16 @@ pk_status pk_sgemv(pk_context *ctx, int64_t M, int64_t N, const float *A, int64_
 
 /* Transpose matrix-vector: y = A^T z (z has M entries, y has N).  Column sums
  * are formed per row block in the workspace and reduced in a fixed order
- * (bitwise reproducible). */
+ * (bitwise reproducible): by a second launch, or, with a one-launch variant, by the
+ * last row block of each column strip to finish.  The workspace needs no clearing
+ * (whatever it held before is overwritten or read as empty); a one-launch variant
+ * needs it 16-byte aligned and otherwise the two-launch default runs instead.
+ * Calls sharing one workspace must not overlap. */
 pk_status pk_sgemv_t(pk_context *ctx, int64_t M, int64_t N, const float *A, int64_t lda,
                      const float *z, float *y, void *ws, size_t ws_bytes, pk_stream stream);
 
-/* The BiCG pair in one pass over A: y1 = A x and y2 = A^T z. */
+/* The BiCG pair in one pass over A: y1 = A x and y2 = A^T z (workspace as for
+ * pk_sgemv_t). */
 pk_status pk_sgemv_pair(pk_context *ctx, int64_t M, int64_t N, const float *A, int64_t lda,
                         const float *x, const float *z, float *y1, float *y2, void *ws,
                         size_t ws_bytes, pk_stream stream);
@@ -212,7 +220,9 @@ pk_status pk_conv3d_3x3x3(pk_context *ctx, int64_t D, int64_t H, int64_t W, cons
 /* CORR's mean/deviation kernels (Sec. 3.4): for the n x m matrix X (n samples,
  * m features), mean_j = (1/n) sum_i x_ij and std_j = max(sqrt((1/(n-1))
  * sum_i (x_ij - mean_j)^2), eps), in FP32 with compensated summation.
- * Requires n >= 2. */
+ * Requires n >= 2.  Per-segment partials in the workspace are merged in a fixed
+ * order, by a second launch or, with a one-launch variant, by the last segment of
+ * each column strip to finish (workspace rules as for pk_sgemv_t). */
 pk_status pk_colstats(pk_context *ctx, int64_t n, int64_t m, const float *X, int64_t ldx,
                       float eps, float *mean, float *std, void *ws, size_t ws_bytes,
                       pk_stream stream);

@@ -22,6 +22,10 @@
 // and B use the same one: lane group g takes the contiguous k range
 // [g*BK/4, (g+1)*BK/4) of the tile, so each lane's operands are one
 // contiguous run in LDS (a single 16-byte read per fragment).
+// With MF = 32 (FP32 only, v_mfma_f32_32x32x2_f32) a block is 32x32: lane l
+// supplies row (and column) l % 32 for the k slot of lane group l / 32, the
+// two groups take the two halves of the tile's k range, and lane l receives
+// column l % 32 of rows 8 (r / 4) + 4 (l / 32) + r % 4, r = 0..15.
 #include "pk_device.h"
 
 #ifndef PREC
@@ -54,18 +58,29 @@
 #ifndef ORDER
 #define ORDER 3
 #endif
+#ifndef MF           // FP32: output block of one MFMA, 16 (v_mfma_f32_16x16x4_f32) or 32
+#define MF 16        // (v_mfma_f32_32x32x2_f32: half the instructions for one wave tile)
+#endif
+#ifndef FC           // FP32: 0 reads a k-step's fragments all at once; 4 reads them four k at a
+#define FC 0         // time, each chunk's MFMAs right after it (deep k-steps in fewer registers)
+#endif
 
 #define FAMILY ((PREC) == 0 ? PKF_GEMM_F32 : ((PREC) == 1 ? PKF_GEMM_BF16 : PKF_GEMM_SPLIT))
 
+static_assert(MF == 16 || (MF == 32 && PREC == 0), "MF 32 is an FP32 form");
 constexpr int NT = 64 * WAVES_M * WAVES_N;
 constexpr int WTM = BM / WAVES_M;
 constexpr int WTN = BN / WAVES_N;
-constexpr int FM = WTM / 16;
-constexpr int FN = WTN / 16;
-constexpr int KI = (PREC == 0) ? 4 : 32;  // depth of one MFMA
-constexpr int KG = BK / 4;                // contiguous k per lane group
+constexpr int BLK = MF;                   // rows / columns of one MFMA output block
+constexpr int NG = 64 / BLK;              // lane groups (k slots of one MFMA)
+constexpr int FM = WTM / BLK;
+constexpr int FN = WTN / BLK;
+constexpr int KI = (PREC == 0) ? NG : 32; // depth of one MFMA
+constexpr int KG = BK / NG;               // contiguous k per lane group
 constexpr int STEPS = BK / KI;            // MFMAs per fragment pair per tile
-static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile must be a multiple of 16");
+static_assert(WTM % BLK == 0 && WTN % BLK == 0, "wave tile must be a multiple of the MFMA block");
+static_assert(PREC != 0 || STEPS % 4 == 0, "FP32 fragments are read four k at a time");
+static_assert(FC == 0 || (FC == 4 && PREC == 0 && STEPS % FC == 0), "FC is 0, or 4 for FP32");
 static_assert(BK % KI == 0 && BK % VEC == 0, "bad BK");
 static_assert(VEC == 1 || VEC == 2 || VEC == 4, "bad VEC");
 static_assert(BN % VEC == 0, "bad BN");
@@ -88,8 +103,9 @@ constexpr int NSPLIT = (PREC == 2) ? 2 : 1;
 constexpr int LDS_STAGES = (USE_LDS == 2) ? 2 : 1;
 constexpr int LDS_BYTES = USE_LDS ? LDS_STAGES * NSPLIT * (BM + BN) * LDK * (int)sizeof(lds_t) : 0;
 
-PK_DEFINE_KNOBS(FAMILY, BM, BN, BK, WAVES_M, WAVES_N, VEC, UNROLL, USE_LDS, ORDER, PREC, 0,
-                NT, LDS_BYTES, PK_KERNEL_ABI_VERSION, 0)
+// knob slot X2 records MF when it is not 16, slot X3 FC
+PK_DEFINE_KNOBS(FAMILY, BM, BN, BK, WAVES_M, WAVES_N, VEC, UNROLL, USE_LDS, ORDER, PREC, (MF == 16 ? 0 : MF),
+                NT, LDS_BYTES, PK_KERNEL_ABI_VERSION, FC)
 
 // map a block index to a (tile row, tile column)
 __device__ __forceinline__ void tile_of(int bid, int tiles_m, int tiles_n, int &tm, int &tn) {
@@ -229,9 +245,20 @@ typedef float frag_t;   // one k slot per MFMA
 #else
 typedef bf16x8 frag_t;  // eight k slots per MFMA
 #endif
+#if MF == 32
+// 32x32 output block: lane l holds column l % 32, rows 8 (r / 4) + 4 (l / 32) + r % 4
+typedef f32x16 acc_t;
+constexpr int ACCN = 16;
+#else
+// 16x16 output block: lane l holds column l % 16, rows 4 (l / 16) + r
+typedef f32x4 acc_t;
+constexpr int ACCN = 4;
+#endif
 
-__device__ __forceinline__ f32x4 mma(frag_t a, frag_t b, f32x4 c) {
-#if PREC == 0
+__device__ __forceinline__ acc_t mma(frag_t a, frag_t b, acc_t c) {
+#if PREC == 0 && MF == 32
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+#elif PREC == 0
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 #else
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -256,6 +283,15 @@ __device__ __forceinline__ void read_frag(const lds_t *S, int row, int g, frag_t
     for (int s = 0; s < STEPS; ++s)
         f[s] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(p + s * 8));
 #endif
+}
+
+// FC = 4: fragments for k slots s0 .. s0+3 of one block row (one 16-byte read)
+__device__ __forceinline__ void read_frag4(const lds_t *S, int row, int g, int s0, frag_t *f) {
+    const f32x4 v = *reinterpret_cast<const f32x4 *>(S + row * LDK + g * KG + s0);
+    f[0] = v[0];
+    f[1] = v[1];
+    f[2] = v[2];
+    f[3] = v[3];
 }
 
 // direct (no LDS) fragment loads from global memory
@@ -332,8 +368,13 @@ __device__ __forceinline__ void gemm_body(const pk_gemm_args &a, lds_t *lds) {
     const int wave = tid >> 6;
     const int wm = wave / WAVES_N;
     const int wn = wave % WAVES_N;
+#if MF == 32
+    const int g = lane >> 5;                   // lane group: its k slot of each MFMA
+    const int lr = lane & 31;                  // row / column of the lane within a block
+#else
     const int g = lane >> 4;
-    const int l16 = lane & 15;
+    const int lr = lane & 15;
+#endif
 
     const int tiles_m = (int)((a.M + BM - 1) / BM);
     const int tiles_n = (int)((a.N + BN - 1) / BN);
@@ -344,12 +385,16 @@ __device__ __forceinline__ void gemm_body(const pk_gemm_args &a, lds_t *lds) {
     const int row0 = tm * BM;
     const int col0 = tn * BN;
 
-    f32x4 acc[FM][FN];
+    acc_t acc[FM][FN];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j)
+#if MF == 32
+            acc[i][j] = f32x16{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#else
             acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#endif
 
     const int64_t nk = (a.K + BK - 1) / BK;
 
@@ -376,22 +421,44 @@ __device__ __forceinline__ void gemm_body(const pk_gemm_args &a, lds_t *lds) {
 #pragma unroll UNROLL
     for (int64_t kt = 0; kt < nk; ++kt) {
         const int cur = (int)(kt & 1);
+#if FC
+#pragma unroll
+        for (int s0 = 0; s0 < STEPS; s0 += FC) {
+            frag_t fa[FM][FC], fb[FN][FC];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+                read_frag4(As_(cur), wm * WTM + i * BLK + lr, g, s0, fa[i]);
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                read_frag4(Bs_(cur), wn * WTN + j * BLK + lr, g, s0, fb[j]);
+#pragma unroll
+            for (int s = 0; s < FC; ++s)
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        acc[i][j] = mma(fa[i][s], fb[j][s], acc[i][j]);
+            // keep the next chunk's fragment reads after these MFMAs are issued, so a
+            // deep k-step holds one chunk of fragments at a time
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#else
         frag_t fa[FM][STEPS], fb[FN][STEPS];
 #if PREC == 2
         frag_t fa2[FM][STEPS], fb2[FN][STEPS];
 #endif
 #pragma unroll
         for (int i = 0; i < FM; ++i) {
-            read_frag(As_(cur), wm * WTM + i * 16 + l16, g, fa[i]);
+            read_frag(As_(cur), wm * WTM + i * BLK + lr, g, fa[i]);
 #if PREC == 2
-            read_frag(As2_(cur), wm * WTM + i * 16 + l16, g, fa2[i]);
+            read_frag(As2_(cur), wm * WTM + i * BLK + lr, g, fa2[i]);
 #endif
         }
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
-            read_frag(Bs_(cur), wn * WTN + j * 16 + l16, g, fb[j]);
+            read_frag(Bs_(cur), wn * WTN + j * BLK + lr, g, fb[j]);
 #if PREC == 2
-            read_frag(Bs2_(cur), wn * WTN + j * 16 + l16, g, fb2[j]);
+            read_frag(Bs2_(cur), wn * WTN + j * BLK + lr, g, fb2[j]);
 #endif
         }
 #pragma unroll
@@ -406,6 +473,7 @@ __device__ __forceinline__ void gemm_body(const pk_gemm_args &a, lds_t *lds) {
 #endif
                     acc[i][j] = mma(fa[i][s], fb[j][s], acc[i][j]);
                 }
+#endif
         if (kt + 1 < nk) {
             store_a<V>(ta, As_(cur ^ 1), As2_(cur ^ 1), tid);
             store_b<V>(tb, Bs_(cur ^ 1), Bs2_(cur ^ 1), tid);
@@ -435,22 +503,46 @@ __device__ __forceinline__ void gemm_body(const pk_gemm_args &a, lds_t *lds) {
             ta.load(a, row0, (kt + 1) * BK, tid);
             tb.load(a, col0, (kt + 1) * BK, tid);
         }
+#if FC
+#pragma unroll
+        for (int s0 = 0; s0 < STEPS; s0 += FC) {
+            frag_t fa[FM][FC], fb[FN][FC];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+                read_frag4(As, wm * WTM + i * BLK + lr, g, s0, fa[i]);
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                read_frag4(Bs, wn * WTN + j * BLK + lr, g, s0, fb[j]);
+#pragma unroll
+            for (int s = 0; s < FC; ++s)
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        acc[i][j] = mma(fa[i][s], fb[j][s], acc[i][j]);
+            // keep the next chunk's fragment reads after these MFMAs are issued, so a
+            // deep k-step holds one chunk of fragments at a time
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        __syncthreads();
+    }
+#else
         frag_t fa[FM][STEPS], fb[FN][STEPS];
 #if PREC == 2
         frag_t fa2[FM][STEPS], fb2[FN][STEPS];
 #endif
 #pragma unroll
         for (int i = 0; i < FM; ++i) {
-            read_frag(As, wm * WTM + i * 16 + l16, g, fa[i]);
+            read_frag(As, wm * WTM + i * BLK + lr, g, fa[i]);
 #if PREC == 2
-            read_frag(As2, wm * WTM + i * 16 + l16, g, fa2[i]);
+            read_frag(As2, wm * WTM + i * BLK + lr, g, fa2[i]);
 #endif
         }
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
-            read_frag(Bs, wn * WTN + j * 16 + l16, g, fb[j]);
+            read_frag(Bs, wn * WTN + j * BLK + lr, g, fb[j]);
 #if PREC == 2
-            read_frag(Bs2, wn * WTN + j * 16 + l16, g, fb2[j]);
+            read_frag(Bs2, wn * WTN + j * BLK + lr, g, fb2[j]);
 #endif
         }
 #pragma unroll
@@ -467,6 +559,7 @@ __device__ __forceinline__ void gemm_body(const pk_gemm_args &a, lds_t *lds) {
                 }
         __syncthreads();
     }
+#endif
 #else
 #pragma unroll UNROLL
     for (int64_t kt = 0; kt < nk; ++kt) {
@@ -475,10 +568,10 @@ __device__ __forceinline__ void gemm_body(const pk_gemm_args &a, lds_t *lds) {
         frag_t fa2[FM][STEPS], fb2[FN][STEPS];
 #pragma unroll
         for (int i = 0; i < FM; ++i)
-            global_frag_a(a, row0 + wm * WTM + i * 16 + l16, kbase, fa[i], fa2[i]);
+            global_frag_a(a, row0 + wm * WTM + i * BLK + lr, kbase, fa[i], fa2[i]);
 #pragma unroll
         for (int j = 0; j < FN; ++j)
-            global_frag_b(a, col0 + wn * WTN + j * 16 + l16, kbase, fb[j], fb2[j]);
+            global_frag_b(a, col0 + wn * WTN + j * BLK + lr, kbase, fb[j], fb2[j]);
 #pragma unroll
         for (int s = 0; s < STEPS; ++s)
 #pragma unroll
@@ -501,10 +594,14 @@ __device__ __forceinline__ void gemm_body(const pk_gemm_args &a, lds_t *lds) {
     for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
-            const int64_t col = col0 + wn * WTN + j * 16 + l16;
+            const int64_t col = col0 + wn * WTN + j * BLK + lr;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
+            for (int r = 0; r < ACCN; ++r) {
+#if MF == 32
+                const int64_t row = row0 + wm * WTM + i * 32 + 8 * (r / 4) + 4 * g + (r % 4);
+#else
                 const int64_t row = row0 + wm * WTM + i * 16 + 4 * g + r;
+#endif
                 if (row < a.M && col < a.N) {
                     float v = a.alpha * acc[i][j][r];
                     if (use_c)

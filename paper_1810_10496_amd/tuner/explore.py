@@ -340,7 +340,25 @@ def _stencil_grids():
     g2 = [dict(TX=tx, VEC=vec, TY=ty, ROWS=rows, UNROLL=1, USE_LDS=0, ORDER=order)
           for tx in (64, 128, 256) for vec in (2, 4) for ty in (1, 2, 4) for rows in (8, 16, 32)
           for order in (0, 2)]
-    return {"conv3d": g3, "conv2d": g2}
+    return {"conv3d": g3, "conv2d": g2, "gemm_f32": _gemm32_grid()}
+
+
+def _gemm32_grid():
+    """The FP32 GEMM around its sampled optimum: 128- and 256-wide tiles, 4 or 8
+    wavefronts, 16x16 or 32x32 MFMA blocks, k steps 16-64 deep (64 with the fragments
+    read four k at a time), one or two LDS stages, row padding 4 or 8 floats."""
+    out = []
+    for bm, bn in ((128, 128), (256, 128), (128, 256), (256, 256)):
+        for wm, wn in ((1, 1), (2, 1), (1, 2), (2, 2), (4, 2), (2, 4)):
+            for bk, fc in ((16, 0), (32, 0), (32, 4), (64, 4)):
+                for lds in (1, 2):
+                    for pad in (4, 8):
+                        for mf in (16, 32):
+                            if mf == 16 and pad == 4 and fc == 0:
+                                continue        # the sampled space
+                            out.append(dict(BM=bm, BN=bn, WAVES_M=wm, WAVES_N=wn, BK=bk, USE_LDS=lds, LDS_PAD=pad,
+                                            MF=mf, FC=fc, VEC=4, UNROLL=1, ORDER=3))
+    return out
 
 
 REFINE_GRIDS = dict(ONE_LAUNCH_GRID, **_stencil_grids())

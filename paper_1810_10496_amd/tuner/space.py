@@ -44,7 +44,10 @@ DOMAINS = {
 #   FUSE: one launch for the transposed matvec, the pair and the column statistics
 #   PF:   planes fetched ahead by the staged 3D stencil
 #   EPI:  the prepared bf16 GEMM's epilogue can write the next product's prepared operand
+#   MF, LDS_PAD, FC: the FP32 GEMM's MFMA block (16 or 32), LDS row padding, fragments
+#   read in chunks of four k (deep k-steps; BK 64, also refine-only, may use the whole LDS)
 REFINE_ONLY = {
+    "gemm_f32": dict(MF=[16, 32], LDS_PAD=[4, 8], FC=[0, 4]),
     "gemv_t": dict(FUSE=[0, 1]),
     "gemv_pair": dict(FUSE=[0, 1]),
     "colstats": dict(FUSE=[0, 1]),
@@ -136,15 +139,20 @@ def valid(family: str, k: dict) -> bool:
         return True
     if family == "gemm_f32":
         wtm, wtn = k["BM"] // k["WAVES_M"], k["BN"] // k["WAVES_N"]
-        if k["BM"] % k["WAVES_M"] or k["BN"] % k["WAVES_N"] or wtm % 16 or wtn % 16:
+        blk = k.get("MF", 16)
+        if k["BM"] % k["WAVES_M"] or k["BN"] % k["WAVES_N"] or wtm % blk or wtn % blk:
             return False
-        if (wtm // 16) * (wtn // 16) > 32:            # accumulator registers per lane <= 128
+        # accumulator registers per lane: <= 128, or <= 256 for the 32x32 blocks (AGPRs)
+        if wtm * wtn // 64 > (256 if blk == 32 else 128):
             return False
-        if k["BN"] % k["VEC"] or k["BK"] % k["VEC"]:
+        if k["BN"] % k["VEC"] or k["BK"] % k["VEC"] or (blk == 32 and k["BK"] % 8):
             return False
         stages = 2 if k["USE_LDS"] == 2 else 1
-        lds = stages * (k["BM"] + k["BN"]) * (k["BK"] + 4) * 4 if k["USE_LDS"] else 0
-        return lds <= LDS_LIMIT and 64 * k["WAVES_M"] * k["WAVES_N"] <= 1024
+        lds = stages * (k["BM"] + k["BN"]) * (k["BK"] + k.get("LDS_PAD", 4)) * 4 if k["USE_LDS"] else 0
+        if k.get("FC", 0) and ((k["BK"] // (64 // blk)) % 4 or blk != 16 and blk != 32):
+            return False
+        limit = LDS_LIMIT_GFX950 if k["BK"] == 64 else LDS_LIMIT
+        return lds <= limit and 64 * k["WAVES_M"] * k["WAVES_N"] <= 1024
     if family == "syrk_f32":
         wtm, wtn = k["BT"] // k["WAVES_M"], k["BT"] // k["WAVES_N"]
         if k["BT"] % k["WAVES_M"] or k["BT"] % k["WAVES_N"] or wtm % 16 or wtn % 16:

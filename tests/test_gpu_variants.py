@@ -36,6 +36,17 @@ VARIANTS = [
     # two LDS stages
     ("gemm_f32", dict(BM=128, BN=128, BK=16, WAVES_M=2, WAVES_N=2, VEC=4, USE_LDS=2, ORDER=3), "default<O3>"),
     ("gemm_f32", dict(BM=64, BN=32, BK=32, WAVES_M=2, WAVES_N=1, VEC=1, USE_LDS=2, ORDER=0), "default<O3>"),
+    # 32x32 MFMA blocks (v_mfma_f32_32x32x2_f32): one and two LDS stages, padding 8, 128x128 wave tiles
+    ("gemm_f32", dict(BM=128, BN=128, BK=16, WAVES_M=2, WAVES_N=2, VEC=4, USE_LDS=1, ORDER=3, MF=32), "default<O3>"),
+    ("gemm_f32", dict(BM=256, BN=128, BK=32, WAVES_M=4, WAVES_N=2, VEC=2, USE_LDS=2, ORDER=0, MF=32, LDS_PAD=8),
+     "default<O3>"),
+    ("gemm_f32", dict(BM=256, BN=256, BK=16, WAVES_M=2, WAVES_N=2, VEC=4, USE_LDS=2, ORDER=2, MF=32), "default<O3>"),
+    ("gemm_f32", dict(BM=64, BN=32, BK=16, WAVES_M=2, WAVES_N=1, VEC=1, USE_LDS=0, ORDER=1, MF=32), "default<O3>"),
+    # 64- and 32-deep k steps with the fragments read four k at a time (16x16 and 32x32 blocks)
+    ("gemm_f32", dict(BM=128, BN=128, BK=64, WAVES_M=2, WAVES_N=2, VEC=4, USE_LDS=1, ORDER=3, FC=4), "default<O3>"),
+    ("gemm_f32", dict(BM=128, BN=256, BK=64, WAVES_M=2, WAVES_N=4, VEC=4, USE_LDS=1, ORDER=3, FC=4, MF=32,
+                      LDS_PAD=8), "default<O3>"),
+    ("gemm_f32", dict(BM=256, BN=128, BK=32, WAVES_M=4, WAVES_N=2, VEC=2, USE_LDS=1, ORDER=0, FC=4), "default<O3>"),
     ("gemv", dict(ROWS=4, WAVES=2, VEC=2, UNROLL=8, USE_LDS=1), "default<O3>"),
     ("gemv_t", dict(ROWS=128, WAVES=8, VEC=1, UNROLL=8, ORDER=1), "default<O2>"),
     ("gemv_pair", dict(ROWS=256, WAVES=1, VEC=2, UNROLL=32, ORDER=1), "default<O3>"),

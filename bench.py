@@ -288,6 +288,43 @@ def stream_ceilings(ctx, dev, stream, rounds=8):
     return out
 
 
+def vendor_blas(dev):
+    """The vendor BLAS (torch.matmul on ROCm: hipBLASLt) at the dense products' sizes, as
+    context for the roofline fractions: FP32 (no reduced-precision shortcut) and BF16,
+    square 2048 and 4096, per-call time from a graph of 20 calls, median of 5 replays."""
+    import torch
+    torch.backends.cuda.matmul.allow_tf32 = False
+    out = []
+    for dt, name, peak in ((torch.float32, "fp32", PEAK_FP32), (torch.bfloat16, "bf16", PEAK_BF16)):
+        for n in (2048, 4096):
+            A = torch.rand(n, n, device=dev).to(dt)
+            B = torch.rand(n, n, device=dev).to(dt)
+            C = torch.empty(n, n, device=dev, dtype=dt)
+            for _ in range(3):
+                torch.matmul(A, B, out=C)
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=s):
+                for _ in range(20):
+                    torch.matmul(A, B, out=C)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(5):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                g.replay()
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1) / 20)
+            t = statistics.median(ts)
+            tf = 2.0 * n ** 3 / (t * 1e-3) / 1e12
+            out.append(dict(dtype=name, n=n, us=round(t * 1e3, 1), tflops=round(tf, 1), frac=round(tf * 1e12 / peak, 4)))
+            del g, A, B, C
+            torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -549,6 +586,8 @@ def main():
         "next_rows": next_rows,
         "gpu_state_before_timing": state,
     }
+    log("timing the vendor BLAS (torch.matmul) at the dense products' sizes, for context")
+    out["vendor_blas"] = vendor_blas(dev)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline()

@@ -64,6 +64,9 @@
 #ifndef FC           // FP32: 0 reads a k-step's fragments all at once; 4 reads them four k at a
 #define FC 0         // time, each chunk's MFMAs right after it (deep k-steps in fewer registers)
 #endif
+#ifndef IL           // FP32, two LDS stages: 1 = full interior tiles run a branch-free k loop whose
+#define IL 0         // LDS stores and global loads are interleaved with the MFMAs (below)
+#endif
 
 #define FAMILY ((PREC) == 0 ? PKF_GEMM_F32 : ((PREC) == 1 ? PKF_GEMM_BF16 : PKF_GEMM_SPLIT))
 
@@ -81,6 +84,7 @@ constexpr int STEPS = BK / KI;            // MFMAs per fragment pair per tile
 static_assert(WTM % BLK == 0 && WTN % BLK == 0, "wave tile must be a multiple of the MFMA block");
 static_assert(PREC != 0 || STEPS % 4 == 0, "FP32 fragments are read four k at a time");
 static_assert(FC == 0 || (FC == 4 && PREC == 0 && STEPS % FC == 0), "FC is 0, or 4 for FP32");
+static_assert(IL == 0 || (PREC == 0 && USE_LDS == 2 && FC == 0), "IL: FP32 with two LDS stages");
 static_assert(BK % KI == 0 && BK % VEC == 0, "bad BK");
 static_assert(VEC == 1 || VEC == 2 || VEC == 4, "bad VEC");
 static_assert(BN % VEC == 0, "bad BN");
@@ -103,9 +107,9 @@ constexpr int NSPLIT = (PREC == 2) ? 2 : 1;
 constexpr int LDS_STAGES = (USE_LDS == 2) ? 2 : 1;
 constexpr int LDS_BYTES = USE_LDS ? LDS_STAGES * NSPLIT * (BM + BN) * LDK * (int)sizeof(lds_t) : 0;
 
-// knob slot X2 records MF when it is not 16, slot X3 FC
-PK_DEFINE_KNOBS(FAMILY, BM, BN, BK, WAVES_M, WAVES_N, VEC, UNROLL, USE_LDS, ORDER, PREC, (MF == 16 ? 0 : MF),
-                NT, LDS_BYTES, PK_KERNEL_ABI_VERSION, FC)
+// knob slot X2 records MF when it is not 16 (+ 1000 with IL), slot X3 FC
+PK_DEFINE_KNOBS(FAMILY, BM, BN, BK, WAVES_M, WAVES_N, VEC, UNROLL, USE_LDS, ORDER, PREC,
+                (MF == 16 ? 0 : MF) + 1000 * IL, NT, LDS_BYTES, PK_KERNEL_ABI_VERSION, FC)
 
 // map a block index to a (tile row, tile column)
 __device__ __forceinline__ void tile_of(int bid, int tiles_m, int tiles_n, int &tm, int &tn) {
@@ -361,6 +365,101 @@ __device__ __forceinline__ void global_frag_b(const pk_gemm_args &a, int64_t col
 #endif
 }
 
+#if IL
+// The k loop of a full interior tile (rows 16-byte aligned, K a multiple of BK, at least
+// two k tiles): no bounds checks, so one iteration is one basic block, and the
+// scheduling-group barriers below lay it out as: the tile's fragment reads, then its
+// MFMAs with the next tile's LDS stores (from registers) and the following tile's global
+// loads (into the same registers, after their stores) interleaved among them, then the
+// barrier.  The last iterations store into the idle stage and re-load the last tile
+// (clamped), which nothing reads.
+constexpr int IL_PA = BM * (BK / 4) / NT;        // A chunks (16 bytes) per thread
+constexpr int IL_PB = BK * (BN / 4) / NT;        // B chunks per thread
+static_assert(IL == 0 || (BM * (BK / 4) % NT == 0 && BK * (BN / 4) % NT == 0), "IL: chunks must divide evenly");
+constexpr int IL_DSR = (FM + FN) * (STEPS / 4);  // 16-byte fragment reads per k tile
+constexpr int IL_MMA = STEPS * FM * FN;          // MFMAs per k tile
+constexpr int IL_DSW = IL_PA + 4 * IL_PB;        // LDS stores per k tile (B is transposed, 4 each)
+constexpr int IL_VMR = IL_PA + IL_PB;            // global loads per k tile
+constexpr int IL_MW = IL_MMA / (2 * IL_DSW) > 0 ? IL_MMA / (2 * IL_DSW) : 1;   // MFMAs before each store
+constexpr int IL_MV = IL_MMA / (4 * IL_VMR) > 0 ? IL_MMA / (4 * IL_VMR) : 1;   // ... before each load
+constexpr int IL_REST = IL_MMA - IL_DSW * IL_MW - IL_VMR * IL_MV;
+
+__device__ __forceinline__ void il_load(const pk_gemm_args &a, int row0, int col0, int64_t k0, int tid,
+                                        f32x4 *ra, f32x4 *rb) {
+#pragma unroll
+    for (int p = 0; p < IL_PA; ++p) {
+        const int q = p * NT + tid;
+        ra[p] = *reinterpret_cast<const f32x4 *>(a.A + (int64_t)(row0 + q / (BK / 4)) * a.lda + k0 + (q % (BK / 4)) * 4);
+    }
+#pragma unroll
+    for (int p = 0; p < IL_PB; ++p) {
+        const int q = p * NT + tid;
+        rb[p] = *reinterpret_cast<const f32x4 *>(a.B + (k0 + q % BK) * a.ldb + col0 + (q / BK) * 4);
+    }
+}
+
+__device__ __forceinline__ void il_store(float *As, float *Bs, int tid, const f32x4 *ra, const f32x4 *rb) {
+#pragma unroll
+    for (int p = 0; p < IL_PA; ++p) {
+        const int q = p * NT + tid;
+        *reinterpret_cast<f32x4 *>(As + (q / (BK / 4)) * LDK + (q % (BK / 4)) * 4) = ra[p];
+    }
+#pragma unroll
+    for (int p = 0; p < IL_PB; ++p) {
+        const int q = p * NT + tid;
+        const int kk = q % BK, c = (q / BK) * 4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            Bs[(c + e) * LDK + kk] = rb[p][e];
+    }
+}
+
+__device__ __forceinline__ void il_main(const pk_gemm_args &a, float *lds, int row0, int col0, int tid, int wm,
+                                        int wn, int g, int lr, acc_t (&acc)[FM][FN]) {
+    constexpr int STAGE = (BM + BN) * LDK;
+    const int64_t nk = a.K / BK;
+    f32x4 ra[IL_PA], rb[IL_PB];
+    il_load(a, row0, col0, 0, tid, ra, rb);
+    il_store(lds, lds + BM * LDK, tid, ra, rb);
+    il_load(a, row0, col0, BK, tid, ra, rb);
+    __syncthreads();
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        const int cur = (int)(kt & 1);
+        const float *As = lds + cur * STAGE, *Bs = lds + cur * STAGE + BM * LDK;
+        float *An = lds + (cur ^ 1) * STAGE, *Bn = lds + (cur ^ 1) * STAGE + BM * LDK;
+        frag_t fa[FM][STEPS], fb[FN][STEPS];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+            read_frag(As, wm * WTM + i * BLK + lr, g, fa[i]);
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+            read_frag(Bs, wn * WTN + j * BLK + lr, g, fb[j]);
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s)
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = mma(fa[i][s], fb[j][s], acc[i][j]);
+        il_store(An, Bn, tid, ra, rb);                              // tile kt+1
+        il_load(a, row0, col0, min(kt + 2, nk - 1) * BK, tid, ra, rb);  // tile kt+2
+        __builtin_amdgcn_sched_group_barrier(0x100, IL_DSR, 0);    // the fragment reads
+#pragma unroll
+        for (int w = 0; w < IL_DSW; ++w) {
+            __builtin_amdgcn_sched_group_barrier(0x008, IL_MW, 0); // MFMAs, then one LDS store
+            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < IL_VMR; ++v) {
+            __builtin_amdgcn_sched_group_barrier(0x008, IL_MV, 0); // MFMAs, then one global load
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, IL_REST, 0);
+        __syncthreads();
+    }
+}
+#endif
+
 template <int V>
 __device__ __forceinline__ void gemm_body(const pk_gemm_args &a, lds_t *lds) {
     const int tid = threadIdx.x;
@@ -398,6 +497,11 @@ __device__ __forceinline__ void gemm_body(const pk_gemm_args &a, lds_t *lds) {
 
     const int64_t nk = (a.K + BK - 1) / BK;
 
+#if IL
+    if (row0 + BM <= a.M && col0 + BN <= a.N && a.K % BK == 0 && nk >= 2 && a.aligned && V == 4) {
+        il_main(a, lds, row0, col0, tid, wm, wn, g, lr, acc);
+    } else {
+#endif
 #if USE_LDS == 2
     // two LDS stages: tile kt+1 is written to the other stage while tile kt is
     // read (its last readers finished before the previous barrier), and the
@@ -586,6 +690,9 @@ __device__ __forceinline__ void gemm_body(const pk_gemm_args &a, lds_t *lds) {
                 }
     }
     (void)V;
+#endif
+#if IL
+    }
 #endif
 
     // epilogue: one store per output element

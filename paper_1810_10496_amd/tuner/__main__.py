@@ -50,6 +50,8 @@ def main(argv=None):
     ap.add_argument("--size", type=int, default=None, help="phase: the size timed (default: the largest)")
     ap.add_argument("--replays", type=int, default=10, help="phase: timed replays per variant")
     ap.add_argument("--build-only", action="store_true", help="phase: compile, do not evaluate")
+    ap.add_argument("--only", action="append", default=[], metavar="KNOB=VALUE",
+                    help="refine: keep only the grid settings with these knob values")
     ap.add_argument("--stage", choices=["host", "gpu"], default="host",
                     help="orders-minimise/permute/cross: the host (compile) or the GPU (timing) half")
     a = ap.parse_args(argv)
@@ -117,7 +119,9 @@ def main(argv=None):
             if fam not in X.REFINE_GRIDS:
                 continue
             tag = "one-launch grid" if fam in X.ONE_LAUNCH_GRID else "structured grid"
-            n = X.refine(fam, a.workdir, path, X.REFINE_GRIDS[fam], sizes, log=log, tag=tag, jobs=a.jobs)
+            only = dict((k, int(v)) for k, v in (o.split("=", 1) for o in a.only))
+            grid = [g for g in X.REFINE_GRIDS[fam] if all(g.get(k) == v for k, v in only.items())]
+            n = X.refine(fam, a.workdir, path, grid, sizes, log=log, tag=tag, jobs=a.jobs)
             log(f"[refine] {fam}: {n} entries replaced")
         return 0
 

@@ -346,7 +346,8 @@ def _stencil_grids():
 def _gemm32_grid():
     """The FP32 GEMM around its sampled optimum: 128- and 256-wide tiles, 4 or 8
     wavefronts, 16x16 or 32x32 MFMA blocks, k steps 16-64 deep (64 with the fragments
-    read four k at a time), one or two LDS stages, row padding 4 or 8 floats."""
+    read four k at a time), one or two LDS stages, row padding 4 or 8 floats; and the
+    same tiles with the interleaved k loop of full tiles (IL)."""
     out = []
     for bm, bn in ((128, 128), (256, 128), (128, 256), (256, 256)):
         for wm, wn in ((1, 1), (2, 1), (1, 2), (2, 2), (4, 2), (2, 4)):
@@ -358,6 +359,12 @@ def _gemm32_grid():
                                 continue        # the sampled space
                             out.append(dict(BM=bm, BN=bn, WAVES_M=wm, WAVES_N=wn, BK=bk, USE_LDS=lds, LDS_PAD=pad,
                                             MF=mf, FC=fc, VEC=4, UNROLL=1, ORDER=3))
+            # the interleaved k loop of full tiles (two LDS stages, whole-fragment reads)
+            for bk in (16, 32):
+                for pad in (4, 8):
+                    for mf in (16, 32):
+                        out.append(dict(BM=bm, BN=bn, WAVES_M=wm, WAVES_N=wn, BK=bk, USE_LDS=2, LDS_PAD=pad,
+                                        MF=mf, FC=0, IL=1, VEC=4, UNROLL=1, ORDER=3))
     return out
 
 

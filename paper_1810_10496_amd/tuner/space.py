@@ -45,9 +45,10 @@ DOMAINS = {
 #   PF:   planes fetched ahead by the staged 3D stencil
 #   EPI:  the prepared bf16 GEMM's epilogue can write the next product's prepared operand
 #   MF, LDS_PAD, FC: the FP32 GEMM's MFMA block (16 or 32), LDS row padding, fragments
-#   read in chunks of four k (deep k-steps; BK 64, also refine-only, may use the whole LDS)
+#   read in chunks of four k (deep k-steps; BK 64, also refine-only, may use the whole LDS);
+#   IL: the interleaved k loop of full interior tiles (two LDS stages)
 REFINE_ONLY = {
-    "gemm_f32": dict(MF=[16, 32], LDS_PAD=[4, 8], FC=[0, 4]),
+    "gemm_f32": dict(MF=[16, 32], LDS_PAD=[4, 8], FC=[0, 4], IL=[0, 1]),
     "gemv_t": dict(FUSE=[0, 1]),
     "gemv_pair": dict(FUSE=[0, 1]),
     "colstats": dict(FUSE=[0, 1]),
@@ -151,7 +152,12 @@ def valid(family: str, k: dict) -> bool:
         lds = stages * (k["BM"] + k["BN"]) * (k["BK"] + k.get("LDS_PAD", 4)) * 4 if k["USE_LDS"] else 0
         if k.get("FC", 0) and ((k["BK"] // (64 // blk)) % 4 or blk != 16 and blk != 32):
             return False
-        limit = LDS_LIMIT_GFX950 if k["BK"] == 64 else LDS_LIMIT
+        if k.get("IL", 0):
+            nt = 64 * k["WAVES_M"] * k["WAVES_N"]
+            if (k["USE_LDS"] != 2 or k.get("FC", 0) or k["VEC"] != 4 or (k["BM"] * k["BK"] // 4) % nt
+                    or (k["BK"] * k["BN"] // 4) % nt):
+                return False
+        limit = LDS_LIMIT_GFX950 if k["BK"] == 64 or k.get("IL", 0) else LDS_LIMIT
         return lds <= limit and 64 * k["WAVES_M"] * k["WAVES_N"] <= 1024
     if family == "syrk_f32":
         wtm, wtn = k["BT"] // k["WAVES_M"], k["BT"] // k["WAVES_N"]

@@ -47,6 +47,14 @@ VARIANTS = [
     ("gemm_f32", dict(BM=128, BN=256, BK=64, WAVES_M=2, WAVES_N=4, VEC=4, USE_LDS=1, ORDER=3, FC=4, MF=32,
                       LDS_PAD=8), "default<O3>"),
     ("gemm_f32", dict(BM=256, BN=128, BK=32, WAVES_M=4, WAVES_N=2, VEC=2, USE_LDS=1, ORDER=0, FC=4), "default<O3>"),
+    # the interleaved k loop of full tiles (edge tiles and ragged K take the general loop)
+    ("gemm_f32", dict(BM=128, BN=128, BK=32, WAVES_M=2, WAVES_N=2, VEC=4, USE_LDS=2, ORDER=3, IL=1), "default<O3>"),
+    ("gemm_f32", dict(BM=256, BN=128, BK=16, WAVES_M=4, WAVES_N=2, VEC=4, USE_LDS=2, ORDER=3, IL=1, LDS_PAD=8),
+     "default<O3>"),
+    ("gemm_f32", dict(BM=128, BN=256, BK=32, WAVES_M=2, WAVES_N=4, VEC=4, USE_LDS=2, ORDER=3, IL=1, MF=32,
+                      LDS_PAD=8), "default<O3>"),
+    ("gemm_f32", dict(BM=256, BN=256, BK=16, WAVES_M=2, WAVES_N=2, VEC=4, USE_LDS=2, ORDER=2, IL=1, MF=32),
+     "default<O3>"),
     ("gemv", dict(ROWS=4, WAVES=2, VEC=2, UNROLL=8, USE_LDS=1), "default<O3>"),
     ("gemv_t", dict(ROWS=128, WAVES=8, VEC=1, UNROLL=8, ORDER=1), "default<O2>"),
     ("gemv_pair", dict(ROWS=256, WAVES=1, VEC=2, UNROLL=32, ORDER=1), "default<O3>"),
@@ -149,7 +157,8 @@ def built():
 def check(ctx, family):
     """Run the family's operation on ragged shapes and compare with the oracle."""
     if family == "gemm_f32":
-        for M, N, K in ((65, 33, 47), (200, 130, 257), (1, 1, 1)):
+        # ragged shapes, and shapes with full interior tiles and K a multiple of every k step
+        for M, N, K in ((65, 33, 47), (200, 130, 257), (1, 1, 1), (300, 260, 96), (256, 256, 512)):
             A, B, C, a, b = synth.gemm_inputs(N, m=M, k=K)
             Cg = g(C)
             ctx.gemm(g(A), g(B), Cg, a, b)

@@ -73,7 +73,7 @@ FAMILIES = {f.name: f for f in [
     _fs("colstats", 8, "colstats.hip", {},
         dict(VEC=4, WAVES=4, ROWS=64, ORDER=0, FUSE=0), "colstats"),
     _fs("syrk_f32", 9, "syrk32.hip", {},
-        dict(BT=64, BK=16, WAVES_M=2, WAVES_N=2, VEC=4, STAGES=2, ORDER=0), "corr"),
+        dict(BT=64, BK=16, WAVES_M=2, WAVES_N=2, VEC=4, STAGES=2, ORDER=0, IL=0), "corr"),
     _fs("syrk_bf16", 10, "gemm_bf.hip", {"PREC": 1, "SYRK": 1},
         dict(BM=128, BN=128, BK=64, WAVES_M=4, WAVES_N=4, ORDER=2, LDS_PAD=8, PIPE=1, DSTAGES=2, SCHED=1),
         "corr", "bf16"),

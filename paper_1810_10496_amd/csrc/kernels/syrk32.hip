@@ -43,6 +43,9 @@
 #ifndef ORDER        // 0: triangle rows in order, 2: XCD-aware groups of 8 tile rows
 #define ORDER 0
 #endif
+#ifndef IL           // two stages: 1 = full tiles run a branch-free k loop whose LDS stores and
+#define IL 0         // global loads are interleaved with the MFMAs (below)
+#endif
 
 constexpr int NT = 64 * WAVES_M * WAVES_N;
 constexpr int WTM = BT / WAVES_M;
@@ -58,8 +61,10 @@ static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile must be a multiple of 1
 static_assert(BK % 4 == 0, "BK must be a multiple of 4");
 static_assert(BT % VEC == 0, "bad VEC");
 static_assert(STAGES == 1 || STAGES == 2, "bad STAGES");
+static_assert(IL == 0 || (STAGES == 2 && (BK * BT / 4) % NT == 0), "IL: two stages, whole chunks per thread");
 
-PK_DEFINE_KNOBS(PKF_SYRK_F32, BT, BT, BK, WAVES_M, WAVES_N, VEC, 1, STAGES, ORDER, 0, 1, NT,
+// knob slot X2 records 1, + 1000 with IL
+PK_DEFINE_KNOBS(PKF_SYRK_F32, BT, BT, BK, WAVES_M, WAVES_N, VEC, 1, STAGES, ORDER, 0, 1 + 1000 * IL, NT,
                 LDS_FLOATS * 4 + 4 * BT * 4, PK_KERNEL_ABI_VERSION, 0)
 
 // block index -> lower-triangle tile (bj >= bk)
@@ -143,6 +148,111 @@ template <int V> struct ZTile {
     }
 };
 
+#if IL
+// The k loop of a full tile (its features inside X, n a multiple of BK, 16-byte aligned
+// rows, at least two k tiles), separately for diagonal blocks (one operand tile) and the
+// others: no bounds checks, so one step is one basic block, and the scheduling-group
+// barriers lay it out as: the step's fragment reads, then its MFMAs with the next tile's
+// normalised LDS stores (from registers) and the following tile's global loads (into the
+// same registers, after their stores) placed between them, then the barrier.  The last
+// step stores into the idle stage and re-loads the last tile (clamped), which nothing
+// reads.  Each thread's columns are fixed, so their means and reciprocal deviations are
+// taken from LDS once, before the loop.
+constexpr int IL_P = BK * BT / 4 / NT;           // 16-byte chunks of one operand tile per thread
+
+__device__ __forceinline__ void il_load(const pk_syrk_args &a, int64_t col0, int64_t i0, int tid, f32x4 *r) {
+#pragma unroll
+    for (int p = 0; p < IL_P; ++p) {
+        const int q = p * NT + tid;
+        r[p] = *reinterpret_cast<const f32x4 *>(a.X + (i0 + q / (BT / 4)) * a.ldx + col0 + (q % (BT / 4)) * 4);
+    }
+}
+
+__device__ __forceinline__ void il_store(float *S, int tid, const f32x4 *r, const f32x4 *mu, const f32x4 *rs) {
+#pragma unroll
+    for (int p = 0; p < IL_P; ++p) {
+        const int q = p * NT + tid;
+        *reinterpret_cast<f32x4 *>(S + (q / (BT / 4)) * LDR + (q % (BT / 4)) * 4) = (r[p] - mu[p]) * rs[p];
+    }
+}
+
+template <bool DIAG>
+__device__ __forceinline__ void il_main(const pk_syrk_args &a, float *lds, int64_t j0, int64_t k0, int tid,
+                                        int wm, int wn, int g, int l16, float (*stat)[BT], f32x4 (&acc)[FM][FN]) {
+    constexpr int OPS = DIAG ? 1 : 2;
+    constexpr int DSR = (BK / 4) * (FM + FN);    // fragment reads per step
+    constexpr int MMA = (BK / 4) * FM * FN;      // MFMAs per step
+    constexpr int DSW = OPS * IL_P;              // LDS stores per step
+    constexpr int VMR = OPS * IL_P;              // global loads per step
+    constexpr int MW = MMA / (2 * DSW) > 0 ? MMA / (2 * DSW) : 1;
+    constexpr int MV = MMA / (4 * VMR) > 0 ? MMA / (4 * VMR) : 1;
+    constexpr int REST = MMA - DSW * MW - VMR * MV;
+    f32x4 muj[IL_P], rsj[IL_P], muk[IL_P], rsk[IL_P];
+#pragma unroll
+    for (int p = 0; p < IL_P; ++p) {
+        const int c = ((p * NT + tid) % (BT / 4)) * 4;
+        muj[p] = f32x4{stat[0][c], stat[0][c + 1], stat[0][c + 2], stat[0][c + 3]};
+        rsj[p] = f32x4{stat[1][c], stat[1][c + 1], stat[1][c + 2], stat[1][c + 3]};
+        muk[p] = f32x4{stat[2][c], stat[2][c + 1], stat[2][c + 2], stat[2][c + 3]};
+        rsk[p] = f32x4{stat[3][c], stat[3][c + 1], stat[3][c + 2], stat[3][c + 3]};
+    }
+    const int64_t nk = a.n / BK;
+    f32x4 rj[IL_P], rk[IL_P];
+    il_load(a, j0, 0, tid, rj);
+    if (!DIAG)
+        il_load(a, k0, 0, tid, rk);
+    il_store(lds, tid, rj, muj, rsj);
+    if (!DIAG)
+        il_store(lds + TILE, tid, rk, muk, rsk);
+    il_load(a, j0, BK, tid, rj);
+    if (!DIAG)
+        il_load(a, k0, BK, tid, rk);
+    __syncthreads();
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        const int cur = (int)(kt & 1);
+        const float *Sj = lds + 2 * cur * TILE, *Sk = DIAG ? Sj : Sj + TILE;
+        float *Nj = lds + 2 * (cur ^ 1) * TILE, *Nk = Nj + TILE;
+        float fa[BK / 4][FM], fb[BK / 4][FN];
+#pragma unroll
+        for (int s = 0; s < BK / 4; ++s) {
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+                fa[s][i] = Sj[(4 * s + g) * LDR + wm * WTM + i * 16 + l16];
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                fb[s][j] = Sk[(4 * s + g) * LDR + wn * WTN + j * 16 + l16];
+        }
+#pragma unroll
+        for (int s = 0; s < BK / 4; ++s)
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[s][i], fb[s][j], acc[i][j], 0, 0, 0);
+        il_store(Nj, tid, rj, muj, rsj);                         // tile kt+1
+        if (!DIAG)
+            il_store(Nk, tid, rk, muk, rsk);
+        const int64_t i2 = min(kt + 2, nk - 1) * BK;             // tile kt+2
+        il_load(a, j0, i2, tid, rj);
+        if (!DIAG)
+            il_load(a, k0, i2, tid, rk);
+        __builtin_amdgcn_sched_group_barrier(0x100, DSR, 0);     // the fragment reads
+#pragma unroll
+        for (int w = 0; w < DSW; ++w) {
+            __builtin_amdgcn_sched_group_barrier(0x008, MW, 0);  // MFMAs, then one LDS store
+            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < VMR; ++v) {
+            __builtin_amdgcn_sched_group_barrier(0x008, MV, 0);  // MFMAs, then one global load
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, REST, 0);
+        __syncthreads();
+    }
+}
+#endif
+
 template <int V>
 __device__ __forceinline__ void syrk32_body(const pk_syrk_args &a, float *lds, float (*stat)[BT]) {
     const int tid = threadIdx.x;
@@ -181,6 +291,14 @@ __device__ __forceinline__ void syrk32_body(const pk_syrk_args &a, float *lds, f
         for (int j = 0; j < FN; ++j)
             acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+#if IL
+    if (j0 + BT <= a.m && k0 + BT <= a.m && a.n % BK == 0 && a.n >= 2 * BK && a.aligned && V == 4) {
+        if (diag)
+            il_main<true>(a, lds, j0, k0, tid, wm, wn, g, l16, stat, acc);
+        else
+            il_main<false>(a, lds, j0, k0, tid, wm, wn, g, l16, stat, acc);
+    } else {
+#endif
     const int64_t nk = (a.n + BK - 1) / BK;
     ZTile<V> tj, tk;
     tj.load(a, j0, 0, tid, stat[0]);
@@ -242,6 +360,9 @@ __device__ __forceinline__ void syrk32_body(const pk_syrk_args &a, float *lds, f
         }
         __syncthreads();
     }
+#if IL
+    }
+#endif
 
     const float denom = (float)(a.n - 1);
 #pragma unroll

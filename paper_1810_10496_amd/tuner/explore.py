@@ -340,7 +340,16 @@ def _stencil_grids():
     g2 = [dict(TX=tx, VEC=vec, TY=ty, ROWS=rows, UNROLL=1, USE_LDS=0, ORDER=order)
           for tx in (64, 128, 256) for vec in (2, 4) for ty in (1, 2, 4) for rows in (8, 16, 32)
           for order in (0, 2)]
-    return {"conv3d": g3, "conv2d": g2, "gemm_f32": _gemm32_grid()}
+    return {"conv3d": g3, "conv2d": g2, "gemm_f32": _gemm32_grid(), "syrk_f32": _syrk32_grid()}
+
+
+def _syrk32_grid():
+    """The FP32 rank-k product of the correlation with the interleaved k loop of full
+    tiles (IL): 64-128-wide triangle tiles, 1-16 wavefronts, 16- or 32-deep k steps, the
+    row-order and the XCD-aware rasters."""
+    return [dict(BT=bt, BK=bk, WAVES_M=wm, WAVES_N=wn, VEC=4, STAGES=2, ORDER=order, IL=1)
+            for bt in (64, 96, 128) for bk in (16, 32)
+            for wm, wn in ((1, 1), (1, 2), (2, 1), (2, 2), (2, 4), (4, 2), (4, 4)) for order in (0, 2)]
 
 
 def _gemm32_grid():

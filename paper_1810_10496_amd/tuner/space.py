@@ -55,6 +55,7 @@ REFINE_ONLY = {
     "conv3d": dict(PF=[1, 2]),
     "gemm_bf16_ws": dict(EPI=[0, 1]),
     "gemm_split_ws": dict(EPI=[0, 1]),
+    "syrk_f32": dict(IL=[0, 1]),
 }
 
 # the reduced-precision contractions: bf16 fragments need BK in multiples of 32
@@ -166,7 +167,9 @@ def valid(family: str, k: dict) -> bool:
         if (wtm // 16) * (wtn // 16) > 32 or k["BT"] % k["VEC"]:
             return False
         ldr = k["BT"] + (16 if k["BT"] % 32 == 0 else 32)
-        return k["STAGES"] * 2 * k["BK"] * ldr * 4 + 16 * k["BT"] <= LDS_LIMIT
+        if k.get("IL", 0) and (k["STAGES"] != 2 or k["VEC"] != 4 or (k["BK"] * k["BT"] // 4) % (64 * k["WAVES_M"] * k["WAVES_N"])):
+            return False
+        return k["STAGES"] * 2 * k["BK"] * ldr * 4 + 16 * k["BT"] <= (LDS_LIMIT_GFX950 if k.get("IL", 0) else LDS_LIMIT)
     if family == "rankk":
         wtm, wtn = k["BT"] // k["WAVES_M"], k["BT"] // k["WAVES_N"]
         if k["BT"] % k["WAVES_M"] or k["BT"] % k["WAVES_N"] or wtm % 16 or wtn % 16:

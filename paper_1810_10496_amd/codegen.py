@@ -61,17 +61,17 @@ FAMILIES = {f.name: f for f in [
     _fs("gemm_split", 2, "gemm_lp.hip", {"PREC": 2},
         dict(BM=256, BN=128, BK=32, WAVES_M=4, WAVES_N=2, VEC=4, STAGES=2, ORDER=3), "gemm", "split"),
     _fs("gemv", 3, "gemv.hip", {"GEMV_KIND": 0},
-        dict(ROWS=1, WAVES=4, VEC=4, UNROLL=4, USE_LDS=0, ORDER=0), "gemv"),
+        dict(ROWS=1, WAVES=4, VEC=4, UNROLL=4, USE_LDS=0, ORDER=0, NTL=0), "gemv"),
     _fs("gemv_t", 4, "gemv.hip", {"GEMV_KIND": 1},
-        dict(ROWS=64, WAVES=4, VEC=4, UNROLL=16, ORDER=0, FUSE=0), "gemv_t"),
+        dict(ROWS=64, WAVES=4, VEC=4, UNROLL=16, ORDER=0, FUSE=0, NTL=0), "gemv_t"),
     _fs("gemv_pair", 5, "gemv.hip", {"GEMV_KIND": 2},
-        dict(ROWS=64, WAVES=4, VEC=4, UNROLL=16, ORDER=0, FUSE=0), "gemv_pair"),
+        dict(ROWS=64, WAVES=4, VEC=4, UNROLL=16, ORDER=0, FUSE=0, NTL=0), "gemv_pair"),
     _fs("conv2d", 6, "conv.hip", {"CONV_KIND": 2},
         dict(VEC=4, TX=64, TY=4, ROWS=8, UNROLL=1, USE_LDS=0, ORDER=0), "conv2d"),
     _fs("conv3d", 7, "conv.hip", {"CONV_KIND": 3},
         dict(VEC=4, TX=64, TY=4, ROWS=16, UNROLL=1, USE_LDS=0, ORDER=0, YR=4, PF=1), "conv3d"),
     _fs("colstats", 8, "colstats.hip", {},
-        dict(VEC=4, WAVES=4, ROWS=64, ORDER=0, FUSE=0), "colstats"),
+        dict(VEC=4, WAVES=4, ROWS=64, ORDER=0, FUSE=0, NTL=0), "colstats"),
     _fs("syrk_f32", 9, "syrk32.hip", {},
         dict(BT=64, BK=16, WAVES_M=2, WAVES_N=2, VEC=4, STAGES=2, ORDER=0, IL=0), "corr"),
     _fs("syrk_bf16", 10, "gemm_bf.hip", {"PREC": 1, "SYRK": 1},
@@ -82,7 +82,7 @@ FAMILIES = {f.name: f for f in [
         "corr", "split"),
     _fs("convert", 12, "convert.hip", {}, dict(VEC=4, NTHREADS=256), "convert"),
     _fs("rankk", 13, "rankk.hip", {}, dict(BT=64, BK=16, WAVES_M=2, WAVES_N=2, VEC=4, UNROLL=1), "syrk"),
-    _fs("gesummv", 14, "gesummv.hip", {}, dict(ROWS=1, WAVES=4, VEC=4, UNROLL=4), "gesummv"),
+    _fs("gesummv", 14, "gesummv.hip", {}, dict(ROWS=1, WAVES=4, VEC=4, UNROLL=4, NTL=0), "gesummv"),
     _fs("fdtd", 15, "fdtd.hip", {}, dict(VEC=4, TX=64, TY=4), "fdtd2d"),
     _fs("gemm_bf16_ws", 16, "gemm_bf.hip", {"PREC": 1},
         dict(BM=256, BN=256, BK=64, WAVES_M=4, WAVES_N=4, ORDER=3, LDS_PAD=8, PIPE=1, DSTAGES=2, SCHED=1, EPI=0),

@@ -30,6 +30,14 @@
 #ifndef FUSE        // 1: one launch (the last segment of each strip merges), 0: + pk_colstats_merge
 #define FUSE 0
 #endif
+#ifndef NTL           // 1: the data matrix is read with the non-temporal hint
+#define NTL 0
+#endif
+#if NTL
+#define PK_LDM pk_ldv_nt
+#else
+#define PK_LDM pk_ldv
+#endif
 
 constexpr int NT = 64 * WAVES;
 constexpr int RPW = (ROWS + WAVES - 1) / WAVES;
@@ -86,7 +94,7 @@ __device__ __forceinline__ void partial_body(const pk_colstats_args &a, float (*
             if (full) {
 #pragma unroll
                 for (int e = 0; e < VEC; e += V)
-                    pk_ldv<V>(a.X + i * a.ldx + c0 + e, v[q] + e);
+                    PK_LDM<V>(a.X + i * a.ldx + c0 + e, v[q] + e);
             } else {
 #pragma unroll
                 for (int e = 0; e < VEC; ++e)

@@ -36,6 +36,14 @@
 #ifndef FUSE          // kinds 1/2: 1 = one launch (the partials are folded by the last
 #define FUSE 0        // block of each strip / row block), 0 = partials + pk_colsum_reduce
 #endif
+#ifndef NTL           // 1: the streamed matrix is read with the non-temporal hint
+#define NTL 0
+#endif
+#if NTL
+#define PK_LDM pk_ldv_nt
+#else
+#define PK_LDM pk_ldv
+#endif
 
 constexpr int NT = 64 * WAVES;
 constexpr int XMAX = 4096;   // x staged in LDS when N <= XMAX
@@ -98,7 +106,7 @@ __device__ __forceinline__ void gemv_body(const pk_gemv_args &a, float *xs) {
             for (int r = 0; r < ROWS; ++r) {
                 const int64_t row = min(row0 + r, a.M - 1);
                 float av[V];
-                pk_ldv<V>(a.A + row * a.lda + j, av);
+                PK_LDM<V>(a.A + row * a.lda + j, av);
 #pragma unroll
                 for (int e = 0; e < V; ++e)
                     acc[r] += av[e] * xv[e];
@@ -236,7 +244,7 @@ __device__ __forceinline__ void colblock_body(const pk_gemvt_args &a) {
                 if (full) {
 #pragma unroll
                     for (int e = 0; e < VEC; e += V)
-                        pk_ldv<V>(a.A + i * a.lda + c0 + e, av + e);
+                        PK_LDM<V>(a.A + i * a.lda + c0 + e, av + e);
                 } else {
 #pragma unroll
                     for (int e = 0; e < VEC; ++e)
@@ -352,7 +360,7 @@ __device__ __forceinline__ void fused_body(const pk_gemvt_args &a) {
                 if (full) {
 #pragma unroll
                     for (int e = 0; e < VEC; e += V)
-                        pk_ldv<V>(a.A + i * a.lda + c0 + e, av + e);
+                        PK_LDM<V>(a.A + i * a.lda + c0 + e, av + e);
                 } else {
 #pragma unroll
                     for (int e = 0; e < VEC; ++e)

@@ -21,6 +21,14 @@
 #ifndef UNROLL
 #define UNROLL 4
 #endif
+#ifndef NTL           // 1: the streamed matrices are read with the non-temporal hint
+#define NTL 0
+#endif
+#if NTL
+#define PK_LDM pk_ldv_nt
+#else
+#define PK_LDM pk_ldv
+#endif
 
 constexpr int NT = 64 * WAVES;
 
@@ -50,8 +58,8 @@ __device__ __forceinline__ void gesummv_body(const pk_gesummv_args &a) {
             for (int r = 0; r < ROWS; ++r) {
                 const int64_t row = min(row0 + r, a.N - 1);
                 float av[V], bv[V];
-                pk_ldv<V>(a.A + row * a.lda + j, av);
-                pk_ldv<V>(a.B + row * a.ldb + j, bv);
+                PK_LDM<V>(a.A + row * a.lda + j, av);
+                PK_LDM<V>(a.B + row * a.ldb + j, bv);
 #pragma unroll
                 for (int e = 0; e < V; ++e) {
                     sa[r] += av[e] * xv[e];

@@ -79,6 +79,21 @@ __device__ __forceinline__ void pk_ldv(const float *p, float *dst) {
     }
 }
 
+// the same load with the non-temporal hint, for data read once: its lines need not
+// displace reusable ones from the caches
+template <int V>
+__device__ __forceinline__ void pk_ldv_nt(const float *p, float *dst) {
+    typedef typename pk_vec<V>::T T;
+    T v = __builtin_nontemporal_load(reinterpret_cast<const T *>(p));
+    if constexpr (V == 1) {
+        dst[0] = v;
+    } else {
+#pragma unroll
+        for (int i = 0; i < V; ++i)
+            dst[i] = v[i];
+    }
+}
+
 template <int V>
 __device__ __forceinline__ void pk_stv(float *p, const float *src) {
     typedef typename pk_vec<V>::T T;

@@ -52,6 +52,9 @@ def main(argv=None):
     ap.add_argument("--build-only", action="store_true", help="phase: compile, do not evaluate")
     ap.add_argument("--only", action="append", default=[], metavar="KNOB=VALUE",
                     help="refine: keep only the grid settings with these knob values")
+    ap.add_argument("--set", action="append", default=[], metavar="KNOB=VALUE",
+                    help="upgrade: rebuild the families' entries with these knobs; an entry is "
+                         "replaced only where that is faster by the margin")
     ap.add_argument("--stage", choices=["host", "gpu"], default="host",
                     help="orders-minimise/permute/cross: the host (compile) or the GPU (timing) half")
     a = ap.parse_args(argv)
@@ -130,6 +133,15 @@ def main(argv=None):
         # which the chained product uses to write T straight into its second product
         from .. import tuned
         path = a.table or tuned.TABLE
+        if a.set:
+            extra = dict((k, int(v)) for k, v in (o.split("=", 1) for o in a.set))
+            for fam in fams:
+                if not all(k in space.REFINE_ONLY.get(fam, {}) or k in space.DOMAINS.get(fam, {}) for k in extra):
+                    continue
+                n = X.upgrade(fam, a.workdir, path, extra, sizes, log=log, tag=f"{extra} upgrade", jobs=a.jobs,
+                              gain=True)
+                log(f"[upgrade] {fam}: {n} entries upgraded")
+            return 0
         for fam in fams:
             if fam in ("gemm_bf16_ws", "gemm_split_ws"):
                 n = X.upgrade(fam, a.workdir, path, dict(EPI=1), sizes, log=log, tag="EPI upgrade", jobs=a.jobs)

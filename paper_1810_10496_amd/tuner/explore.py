@@ -468,11 +468,13 @@ def refine(family, workdir, table_path, grid, sizes=(256, 512, 1000, 2048, 4096)
 
 
 def upgrade(family, workdir, table_path, extra, sizes=(256, 512, 1000, 2048, 4096), replays=30, seeds=30,
-            eval_timeout=300.0, log=print, margin=0.03, jobs=8, tag="upgraded"):
-    """Rebuild each non-default table entry with the knobs `extra` added (a capability
-    that leaves the entry's own launches unchanged, e.g. EPI) and take the rebuilt code
-    object if, re-timed with `replays` replays beside the entry, it is not slower than
-    the entry by more than `margin` and it passes the `seeds`-seed validation."""
+            eval_timeout=300.0, log=print, margin=0.03, jobs=8, tag="upgraded", gain=False):
+    """Rebuild each non-default table entry with the knobs `extra` added, keeping its
+    pipeline and flags, and take the rebuilt code object if, re-timed with `replays`
+    replays beside the entry, it passes the `seeds`-seed validation and is not slower
+    than the entry by more than `margin` (a capability that leaves the entry's own
+    launches unchanged, e.g. EPI) or, with `gain`, is faster by at least `margin` (a
+    knob that is there for speed alone, e.g. NTL)."""
     from .. import tuned
     from ..api import Context
     db = DB(os.path.join(workdir, "db.jsonl"))
@@ -506,7 +508,7 @@ def upgrade(family, workdir, table_path, extra, sizes=(256, 512, 1000, 2048, 409
                           eval_timeout, replays=replays, validate=False)
             t_cur, t_new = c["times"].get(key, math.inf), n["times"].get(key, math.inf)
             log(f"[upgrade] {family}/{size}: entry {t_cur:.4f} ms, with {extra} {t_new:.4f} ms")
-            if not t_new <= t_cur * (1.0 + margin):
+            if not t_new <= t_cur * ((1.0 - margin) if gain else (1.0 + margin)):
                 continue
             val = _evaluate(ev, db, family, rec["sha"], _co_path(workdir, family, rec["sha"]), [], None,
                             eval_timeout, validate=True, seeds=seeds)

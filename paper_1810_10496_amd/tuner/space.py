@@ -49,9 +49,11 @@ DOMAINS = {
 #   IL: the interleaved k loop of full interior tiles (two LDS stages)
 REFINE_ONLY = {
     "gemm_f32": dict(MF=[16, 32], LDS_PAD=[4, 8], FC=[0, 4], IL=[0, 1]),
-    "gemv_t": dict(FUSE=[0, 1]),
-    "gemv_pair": dict(FUSE=[0, 1]),
-    "colstats": dict(FUSE=[0, 1]),
+    "gemv": dict(NTL=[0, 1]),
+    "gemv_t": dict(FUSE=[0, 1], NTL=[0, 1]),
+    "gemv_pair": dict(FUSE=[0, 1], NTL=[0, 1]),
+    "colstats": dict(FUSE=[0, 1], NTL=[0, 1]),
+    "gesummv": dict(NTL=[0, 1]),
     "conv3d": dict(PF=[1, 2]),
     "gemm_bf16_ws": dict(EPI=[0, 1]),
     "gemm_split_ws": dict(EPI=[0, 1]),

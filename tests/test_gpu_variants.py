@@ -64,6 +64,13 @@ VARIANTS = [
     ("conv3d", dict(VEC=4, TX=64, TY=4, ROWS=8, USE_LDS=1), "default<O3>"),
     ("conv3d", dict(VEC=2, TX=16, TY=16, ROWS=32, USE_LDS=1, ORDER=1), "default<O3>"),
     ("colstats", dict(VEC=2, WAVES=8, ROWS=256, ORDER=1), "default<O3>"),
+    # the streamed matrix read with the non-temporal hint (the two-launch and the
+    # one-launch matrix-vector forms, the column statistics, GESUMMV)
+    ("gemv", dict(ROWS=2, WAVES=4, VEC=4, UNROLL=4, NTL=1), "default<O3>"),
+    ("gemv_t", dict(ROWS=64, WAVES=2, VEC=2, UNROLL=16, ORDER=1, NTL=1), "default<O3>"),
+    ("gemv_pair", dict(ROWS=64, WAVES=4, VEC=2, UNROLL=16, ORDER=0, FUSE=1, NTL=1), "default<O3>"),
+    ("colstats", dict(VEC=2, WAVES=8, ROWS=64, ORDER=0, NTL=1), "default<O3>"),
+    ("gesummv", dict(ROWS=2, WAVES=4, VEC=4, UNROLL=2, NTL=1), "default<O3>"),
     ("syrk_f32", dict(BT=128, BK=32, WAVES_M=2, WAVES_N=2, VEC=4, STAGES=2), "default<O3>"),
     ("syrk_f32", dict(BT=32, BK=16, WAVES_M=2, WAVES_N=1, VEC=1, STAGES=1), ORDER),
     # XCD-aware tile orders (tile counts that are and are not multiples of 8)
@@ -210,6 +217,12 @@ def check(ctx, family):
             mu, sd = ctx.colstats(g(X), eps)
             mr, sr = o.colstats(X, eps)
             assert o.max_err(h(mu), mr, o.colstats(np.abs(X), eps)[0]) <= 1e-6 and o.max_err(h(sd), sr) <= 1e-5
+    elif family == "gesummv":
+        for N in (1, 130, 1000, 4097):
+            A, B, x = synth.uniform(871, (N, N)), synth.uniform(872, (N, N)), synth.uniform(873, (N,))
+            y = ctx.gesummv(g(A), g(B), g(x), 1.5, 1.2)
+            scale = o.gesummv(np.abs(A), np.abs(B), np.abs(x), 1.5, 1.2)
+            assert o.max_err(h(y), o.gesummv(A, B, x, 1.5, 1.2), scale) <= 1e-4
     elif family in ("syrk_f32", "syrk_bf16", "syrk_split"):
         prec = {"syrk_f32": "fp32", "syrk_bf16": "bf16", "syrk_split": "split"}[family]
         tol = {"fp32": 1e-4, "bf16": 2e-2, "split": 1e-5}[prec]

@@ -67,9 +67,9 @@ FAMILIES = {f.name: f for f in [
     _fs("gemv_pair", 5, "gemv.hip", {"GEMV_KIND": 2},
         dict(ROWS=64, WAVES=4, VEC=4, UNROLL=16, ORDER=0, FUSE=0, NTL=0), "gemv_pair"),
     _fs("conv2d", 6, "conv.hip", {"CONV_KIND": 2},
-        dict(VEC=4, TX=64, TY=4, ROWS=8, UNROLL=1, USE_LDS=0, ORDER=0), "conv2d"),
+        dict(VEC=4, TX=64, TY=4, ROWS=8, UNROLL=1, USE_LDS=0, ORDER=0, NTL=0), "conv2d"),
     _fs("conv3d", 7, "conv.hip", {"CONV_KIND": 3},
-        dict(VEC=4, TX=64, TY=4, ROWS=16, UNROLL=1, USE_LDS=0, ORDER=0, YR=4, PF=1), "conv3d"),
+        dict(VEC=4, TX=64, TY=4, ROWS=16, UNROLL=1, USE_LDS=0, ORDER=0, YR=4, PF=1, NTL=0), "conv3d"),
     _fs("colstats", 8, "colstats.hip", {},
         dict(VEC=4, WAVES=4, ROWS=64, ORDER=0, FUSE=0, NTL=0), "colstats"),
     _fs("syrk_f32", 9, "syrk32.hip", {},

@@ -36,6 +36,14 @@
 #ifndef ORDER       // 0: x tiles fastest, 1: y tiles fastest, 2: x fastest, XCD-contiguous
 #define ORDER 0
 #endif
+#ifndef NTL         // 1: the input's row segments are read with the non-temporal hint
+#define NTL 0
+#endif
+#if NTL
+#define PK_LDM pk_ldv_nt
+#else
+#define PK_LDM pk_ldv
+#endif
 
 constexpr int NT = TX * TY;
 static_assert(NT % 64 == 0, "block must be whole wavefronts");
@@ -69,7 +77,7 @@ __device__ __forceinline__ void load_seg(const pk_conv2d_args &a, int64_t y, int
     if (x0 + VEC <= a.W) {
 #pragma unroll
         for (int e = 0; e < VEC; e += V)
-            pk_ldv<V>(row + x0 + e, s + 1 + e);
+            PK_LDM<V>(row + x0 + e, s + 1 + e);
     } else {
 #pragma unroll
         for (int e = 0; e < VEC; ++e)
@@ -254,7 +262,7 @@ __device__ __forceinline__ void load_plane(const pk_conv3d_args &a, int64_t z, i
         if (x0 + VEC <= a.W) {
 #pragma unroll
             for (int e = 0; e < VEC; e += V)
-                pk_ldv<V>(row + x0 + e, p[dy] + 1 + e);
+                PK_LDM<V>(row + x0 + e, p[dy] + 1 + e);
         } else {
 #pragma unroll
             for (int e = 0; e < VEC; ++e)
@@ -449,7 +457,7 @@ template <int CV> struct PlaneTile {
             const int r = q / (BX / CV), c = (q % (BX / CV)) * CV;
             const int64_t gy = gy0 + r, gx = gx0 + c;
             if (q < NV && zin && gy >= 0 && gy < a.H && gx + CV <= a.W) {
-                pk_ldv<CV>(a.in + (z * a.H + gy) * a.W + gx, v[p]);
+                PK_LDM<CV>(a.in + (z * a.H + gy) * a.W + gx, v[p]);
             } else {
 #pragma unroll
                 for (int e = 0; e < CV; ++e)

@@ -488,27 +488,38 @@ def upgrade(family, workdir, table_path, extra, sizes=(256, 512, 1000, 2048, 409
             key = str(size)
             bucket = Context.size_bucket(size)
             idx = [i for i, e in enumerate(entries) if e["family"] == family and int(e["bucket"]) == bucket]
-            if len(idx) != 1 or entries[idx[0]].get("is_default"):
+            # an entry that kept the default is a candidate only for a knob that must gain:
+            # then the family's default, with the knobs added, is timed against the default
+            if len(idx) != 1 or (entries[idx[0]].get("is_default") and not gain):
                 continue
             cur = entries[idx[0]]
             v = space.Variant(family, dict(cur["knobs"], **extra), cur["pipeline"],
                               tuple(cur.get("llc_flags", ["-O3"])), tuple(cur.get("opt_flags", [])))
             rec = _build_many(db, [v], workdir, jobs)[0]
-            code = tuned.code_for(cur)
+            if cur.get("is_default"):
+                base = _build_many(db, [space.Variant(family, space.default_knobs(family), codegen.DEFAULT_PIPELINE)],
+                                   workdir, jobs)[0]
+                cur_sha = base["sha"] if base["status"] == "ok" else None
+                code = True if cur_sha else None
+            else:
+                cur_sha = cur["code_sha256"]
+                code = tuned.code_for(cur)
             if rec["status"] != "ok" or code is None:
                 log(f"[upgrade] {family}/{size}: not built ({rec['status']}) or the entry does not reproduce")
                 continue
-            p = _co_path(workdir, family, cur["code_sha256"])
-            os.makedirs(os.path.dirname(p), exist_ok=True)
-            with open(p, "wb") as f:
-                f.write(code)
-            c = _evaluate(ev, db, family, cur["code_sha256"], p, [size], None, eval_timeout, replays=replays,
+            p = _co_path(workdir, family, cur_sha)
+            if code is not True:
+                os.makedirs(os.path.dirname(p), exist_ok=True)
+                with open(p, "wb") as f:
+                    f.write(code)
+            c = _evaluate(ev, db, family, cur_sha, p, [size], None, eval_timeout, replays=replays,
                           validate=False)
             n = _evaluate(ev, db, family, rec["sha"], _co_path(workdir, family, rec["sha"]), [size], None,
                           eval_timeout, replays=replays, validate=False)
             t_cur, t_new = c["times"].get(key, math.inf), n["times"].get(key, math.inf)
             log(f"[upgrade] {family}/{size}: entry {t_cur:.4f} ms, with {extra} {t_new:.4f} ms")
-            if not t_new <= t_cur * ((1.0 - margin) if gain else (1.0 + margin)):
+            if not (math.isfinite(t_cur) and math.isfinite(t_new)) or \
+                    not t_new <= t_cur * ((1.0 - margin) if gain else (1.0 + margin)):
                 continue
             val = _evaluate(ev, db, family, rec["sha"], _co_path(workdir, family, rec["sha"]), [], None,
                             eval_timeout, validate=True, seeds=seeds)
@@ -516,7 +527,8 @@ def upgrade(family, workdir, table_path, extra, sizes=(256, 512, 1000, 2048, 409
                 log(f"[upgrade] {family}/{size}: failed the {seeds}-seed validation")
                 continue
             entries[idx[0]] = dict(cur, knobs=v.knobs, code_sha256=rec["sha"], tuned_ms=t_new,
-                                   speedup=cur["default_ms"] / t_new, source=tag)
+                                   speedup=cur["default_ms"] / t_new, source=tag, is_default=False,
+                                   llc_flags=list(v.llc_flags), opt_flags=list(v.opt_flags))
             changed += 1
     finally:
         ev.close()

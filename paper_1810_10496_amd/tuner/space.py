@@ -54,7 +54,8 @@ REFINE_ONLY = {
     "gemv_pair": dict(FUSE=[0, 1], NTL=[0, 1]),
     "colstats": dict(FUSE=[0, 1], NTL=[0, 1]),
     "gesummv": dict(NTL=[0, 1]),
-    "conv3d": dict(PF=[1, 2]),
+    "conv2d": dict(NTL=[0, 1]),
+    "conv3d": dict(PF=[1, 2], NTL=[0, 1]),
     "gemm_bf16_ws": dict(EPI=[0, 1]),
     "gemm_split_ws": dict(EPI=[0, 1]),
     "syrk_f32": dict(IL=[0, 1]),

@@ -71,6 +71,9 @@ VARIANTS = [
     ("gemv_pair", dict(ROWS=64, WAVES=4, VEC=2, UNROLL=16, ORDER=0, FUSE=1, NTL=1), "default<O3>"),
     ("colstats", dict(VEC=2, WAVES=8, ROWS=64, ORDER=0, NTL=1), "default<O3>"),
     ("gesummv", dict(ROWS=2, WAVES=4, VEC=4, UNROLL=2, NTL=1), "default<O3>"),
+    ("conv2d", dict(VEC=4, TX=64, TY=4, ROWS=8, NTL=1), "default<O3>"),
+    ("conv3d", dict(VEC=4, TX=64, TY=4, ROWS=16, NTL=1), "default<O3>"),
+    ("conv3d", dict(VEC=2, TX=64, TY=4, YR=4, ROWS=16, USE_LDS=2, ORDER=1, NTL=1), "default<O3>"),
     ("syrk_f32", dict(BT=128, BK=32, WAVES_M=2, WAVES_N=2, VEC=4, STAGES=2), "default<O3>"),
     ("syrk_f32", dict(BT=32, BK=16, WAVES_M=2, WAVES_N=1, VEC=1, STAGES=1), ORDER),
     # XCD-aware tile orders (tile counts that are and are not multiples of 8)

@@ -35,7 +35,7 @@ def main(argv=None):
     ap.add_argument("cmd", choices=["passes", "gpu-filter", "explore", "finalize", "refine", "upgrade", "reuse", "table", "report",
                                         "study", "phase", "orders-build", "orders-eval", "orders-finalize",
                                         "orders-minimise", "orders-permute", "orders-cross", "orders-table",
-                                        "orders-report"])
+                                        "orders-report", "table-report"])
     ap.add_argument("--workdir", default="tune_work")
     ap.add_argument("--families", default=",".join(workloads.TUNED_FAMILIES))
     ap.add_argument("--samples", type=int, default=500)
@@ -211,6 +211,15 @@ def main(argv=None):
             else:
                 log(text)
         return 0
+    if a.cmd == "table-report":
+        from .. import tuned
+        from .study import table_report
+        out = a.out or os.path.join(os.path.dirname(tuned.TABLE), "table.md")
+        with open(out, "w") as f:
+            f.write(table_report(a.table or tuned.TABLE))
+        log(f"[table-report] -> {out}")
+        return 0
+
     if a.cmd == "report":
         db = X.DB(os.path.join(a.workdir, "db.jsonl"))
         rep = {fam: X.census(db, fam) for fam in fams}

@@ -229,3 +229,51 @@ def study(workdir, families, samples=500, seed=5500, note=None, explored=None):
                 f"{r['cosine_k1']:.3f}x, K=3 {r['cosine_k3']:.3f}x; random K=1 {r['random_k1']:.3f}x, "
                 f"K=3 {r['random_k3']:.3f}x (1000 draws)"]
     return "\n".join(out) + "\n"
+
+
+def table_report(table_path) -> str:
+    """The finished tuning table as a report: per family and size the tuned / default
+    speedup the table records and the step that chose the entry (the seeded exploration's
+    finalize, a structured or one-launch `refine` grid, or an `upgrade`), and the entry's
+    knobs where a later step changed them.  Written from the table alone."""
+    with open(table_path) as f:
+        doc = json.load(f)
+    ents = doc["entries"]
+    fams = sorted({e["family"] for e in ents})
+    sizes = sorted({int(e["size"]) for e in ents})
+    by = {(e["family"], int(e["size"])): e for e in ents}
+
+    def step(e):
+        if e.get("is_default"):
+            return "default kept"
+        src = e.get("source")
+        return src if src else "finalize"
+
+    out = ["# The tuning table (tuned/best.json)", "",
+           "Speedup of the selected variant over the family's default at each size, as the step "
+           "that selected it measured it (finalize: the seeded exploration's finalists, 30 "
+           "replays; refine and upgrade: 30 replays beside the entry they replaced, which they "
+           "beat by the 3% margin or, for a capability, matched within it).  Written by "
+           "`python -m paper_1810_10496_amd.tuner table-report`.", "",
+           "| family | " + " | ".join(str(s) for s in sizes) + " |",
+           "|---|" + "---:|" * len(sizes)]
+    for fam in fams:
+        cells = []
+        for s in sizes:
+            e = by.get((fam, s))
+            cells.append("—" if e is None else ("1.00x (default)" if e.get("is_default")
+                                               else f"{float(e['speedup']):.2f}x"))
+        out.append(f"| {fam} | " + " | ".join(cells) + " |")
+    counts = collections.Counter(step(e) for e in ents)
+    out += ["", "## Which step selected each entry", "",
+            "| step | entries |", "|---|---:|"]
+    out += [f"| {k} | {counts[k]} |" for k in sorted(counts)]
+    later = [e for e in ents if e.get("source")]
+    if later:
+        out += ["", "## Entries selected after the exploration", "",
+                "| family | size | step | tuned ms | speedup | knobs |", "|---|---:|---|---:|---:|---|"]
+        for e in sorted(later, key=lambda e: (e["family"], int(e["size"]))):
+            ks = ", ".join(f"{k}={v}" for k, v in sorted(e["knobs"].items()))
+            out.append(f"| {e['family']} | {e['size']} | {e['source']} | {float(e['tuned_ms']):.4f} | "
+                       f"{float(e['speedup']):.2f}x | {ks} |")
+    return "\n".join(out) + "\n"

@@ -533,3 +533,12 @@ def test_minimise_gpu_keeps_the_passes_that_pay(tmp_path):
     assert m["minimal"] == ["fast1", "fast2"]
     assert m["how"] == "removed together"
     assert {x["removed"] for x in m["singles"] if not x["removable"]} == {"fast1", "fast2"}
+
+
+def test_table_report_matches_the_table():
+    """tuned/table.md is the report of the committed table (regenerate it with
+    `tuner table-report` after any table change)."""
+    from paper_1810_10496_amd import tuned
+    from paper_1810_10496_amd.tuner.study import table_report
+    path = os.path.join(os.path.dirname(tuned.TABLE), "table.md")
+    assert open(path).read() == table_report(tuned.TABLE)

@@ -71,7 +71,7 @@ FAMILIES = {f.name: f for f in [
     _fs("conv3d", 7, "conv.hip", {"CONV_KIND": 3},
         dict(VEC=4, TX=64, TY=4, ROWS=16, UNROLL=1, USE_LDS=0, ORDER=0, YR=4, PF=1, NTL=0), "conv3d"),
     _fs("colstats", 8, "colstats.hip", {},
-        dict(VEC=4, WAVES=4, ROWS=64, ORDER=0, FUSE=0, NTL=0), "colstats"),
+        dict(VEC=4, WAVES=4, ROWS=64, ORDER=0, FUSE=0, NTL=0, MG=0), "colstats"),
     _fs("syrk_f32", 9, "syrk32.hip", {},
         dict(BT=64, BK=16, WAVES_M=2, WAVES_N=2, VEC=4, STAGES=2, ORDER=0, IL=0), "corr"),
     _fs("syrk_bf16", 10, "gemm_bf.hip", {"PREC": 1, "SYRK": 1},

@@ -30,6 +30,9 @@
 #ifndef FUSE        // 1: one launch (the last segment of each strip merges), 0: + pk_colstats_merge
 #define FUSE 0
 #endif
+#ifndef MG          // the two-launch merge: 0 = two passes about the total mean, 1 = one pass
+#define MG 0        // (pairwise count / mean / M2 combination), loading only existing segments
+#endif
 #ifndef NTL           // 1: the data matrix is read with the non-temporal hint
 #define NTL 0
 #endif
@@ -340,6 +343,93 @@ extern "C" __global__ void __launch_bounds__(NT) pk_colstats_partial(pk_colstats
         partial_body<1>(a, red, smean);
 }
 
+#if MG
+// The merge in one pass: a block is MW wavefronts over 64 columns (lane = column).
+// Wavefront w folds the segments b = w, w+MW, ... in ascending order, loading only those
+// that exist (the bound is the same for the whole wavefront), MQ1 at a time, into
+//  - a compensated total: the (hi, lo) terms by Neumaier summation, from which the mean
+//    is taken, and
+//  - the pairwise combination of (count, mean, M2) (Chan, Golub and LeVeque): a
+//    segment's mean is its compensated sum over its rows, and merging (n_a, mu_a, M2_a)
+//    with (n_b, mu_b, M2_b) gives M2_a + M2_b + d^2 n_a n_b / (n_a + n_b), d = mu_b - mu_a
+//    (every term >= 0, so the large column offsets never cancel).
+// After one barrier the MW partial results of a column are combined in the order
+// w = 0..MW-1, so the result does not depend on timing.
+constexpr int MQ1 = 8;
+
+__device__ __forceinline__ void chan_merge(float &cnt, float &mu, float &m2, float nb, float mb, float m2b) {
+    if (nb > 0.f) {
+        if (cnt == 0.f) {
+            cnt = nb;
+            mu = mb;
+            m2 = m2b;
+        } else {
+            const float t = cnt + nb;
+            const float rt = 1.0f / t;
+            const float d = mb - mu;
+            mu += d * nb * rt;
+            m2 += m2b + d * d * (cnt * nb * rt);
+            cnt = t;
+        }
+    }
+}
+
+extern "C" __global__ void __launch_bounds__(64 * MW) pk_colstats_merge(pk_colstats_args a) {
+    if (blockDim.x != 64 * MW)
+        return;
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    __shared__ float sh[5][MW][64];
+    for (int64_t c0 = (int64_t)blockIdx.x * 64; c0 < a.m; c0 += (int64_t)gridDim.x * 64) {
+        const int64_t j = c0 + lane;
+        const bool valid = j < a.m;
+        const int64_t jr = valid ? j : a.m - 1;          // lanes past m read column m-1
+        float hi = 0.f, lo = 0.f, cnt = 0.f, mu = 0.f, m2 = 0.f;
+        for (int b0 = w; b0 < a.segments; b0 += MQ1 * MW) {
+            float hv[MQ1], lv[MQ1], mv[MQ1];
+#pragma unroll
+            for (int q = 0; q < MQ1; ++q) {
+                const int b = b0 + q * MW;
+                if (b < a.segments) {
+                    const float *p = a.part + (int64_t)b * 3 * a.m;
+                    hv[q] = p[jr];
+                    lv[q] = p[a.m + jr];
+                    mv[q] = p[2 * a.m + jr];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < MQ1; ++q) {
+                const int b = b0 + q * MW;
+                if (b < a.segments) {
+                    pk_neumaier(hi, lo, hv[q]);
+                    pk_neumaier(hi, lo, lv[q]);
+                    const int64_t r0 = (int64_t)b * a.seg_rows;
+                    const float nb = (float)(min(r0 + (int64_t)a.seg_rows, a.n) - r0);
+                    chan_merge(cnt, mu, m2, nb, (hv[q] + lv[q]) / nb, mv[q]);
+                }
+            }
+        }
+        sh[0][w][lane] = hi;
+        sh[1][w][lane] = lo;
+        sh[2][w][lane] = cnt;
+        sh[3][w][lane] = mu;
+        sh[4][w][lane] = m2;
+        __syncthreads();
+        if (w == 0 && valid) {
+            float th = 0.f, tl = 0.f, tc = 0.f, tm = 0.f, t2 = 0.f;
+#pragma unroll
+            for (int q = 0; q < MW; ++q) {
+                pk_neumaier(th, tl, sh[0][q][lane]);
+                pk_neumaier(th, tl, sh[1][q][lane]);
+                chan_merge(tc, tm, t2, sh[2][q][lane], sh[3][q][lane], sh[4][q][lane]);
+            }
+            a.mean[j] = (th + tl) / (float)a.n;
+            a.std[j] = fmaxf(sqrtf(t2 / (float)(a.n - 1)), a.eps);
+        }
+        __syncthreads();
+    }
+}
+#else
 // The merge: a block is MW wavefronts over 64 columns (lane = column).  Wavefront w
 // takes the segments b = w, w+MW, ... in ascending order; it loads the (hi, lo, M2)
 // of up to MQ of them at once into registers and folds them from there, so both
@@ -437,3 +527,4 @@ extern "C" __global__ void __launch_bounds__(64 * MW) pk_colstats_merge(pk_colst
         __syncthreads();
     }
 }
+#endif

@@ -495,6 +495,9 @@ def upgrade(family, workdir, table_path, extra, sizes=(256, 512, 1000, 2048, 409
             cur = entries[idx[0]]
             v = space.Variant(family, dict(cur["knobs"], **extra), cur["pipeline"],
                               tuple(cur.get("llc_flags", ["-O3"])), tuple(cur.get("opt_flags", [])))
+            if not space.valid(family, dict(space.default_knobs(family), **v.knobs)):
+                log(f"[upgrade] {family}/{size}: {extra} does not combine with the entry's knobs")
+                continue
             rec = _build_many(db, [v], workdir, jobs)[0]
             if cur.get("is_default"):
                 base = _build_many(db, [space.Variant(family, space.default_knobs(family), codegen.DEFAULT_PIPELINE)],

@@ -52,7 +52,7 @@ REFINE_ONLY = {
     "gemv": dict(NTL=[0, 1]),
     "gemv_t": dict(FUSE=[0, 1], NTL=[0, 1]),
     "gemv_pair": dict(FUSE=[0, 1], NTL=[0, 1]),
-    "colstats": dict(FUSE=[0, 1], NTL=[0, 1]),
+    "colstats": dict(FUSE=[0, 1], NTL=[0, 1], MG=[0, 1]),
     "gesummv": dict(NTL=[0, 1]),
     "conv2d": dict(NTL=[0, 1]),
     "conv3d": dict(PF=[1, 2], NTL=[0, 1]),
@@ -206,6 +206,8 @@ def valid(family: str, k: dict) -> bool:
             return 3 * (k["TY"] + 2) * (k["TX"] * k["VEC"] + 4) * 4 <= LDS_LIMIT
         return True
     if family == "colstats":
+        if k.get("MG", 0) and k.get("FUSE", 0):
+            return False                     # the one-launch form has no separate merge
         rpw = -(-k["ROWS"] // k["WAVES"])
         lds = (3 * k["WAVES"] + 1) * 64 * k["VEC"] * 4
         return rpw * k["VEC"] <= 128 and lds <= LDS_LIMIT

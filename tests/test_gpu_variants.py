@@ -71,6 +71,9 @@ VARIANTS = [
     ("gemv_pair", dict(ROWS=64, WAVES=4, VEC=2, UNROLL=16, ORDER=0, FUSE=1, NTL=1), "default<O3>"),
     ("colstats", dict(VEC=2, WAVES=8, ROWS=64, ORDER=0, NTL=1), "default<O3>"),
     ("gesummv", dict(ROWS=2, WAVES=4, VEC=4, UNROLL=2, NTL=1), "default<O3>"),
+    # the one-pass merge of the column statistics (many, few and one segment per column)
+    ("colstats", dict(VEC=1, WAVES=4, ROWS=16, ORDER=0, MG=1), "default<O3>"),
+    ("colstats", dict(VEC=2, WAVES=8, ROWS=64, ORDER=0, NTL=1, MG=1), "default<O3>"),
     ("conv2d", dict(VEC=4, TX=64, TY=4, ROWS=8, NTL=1), "default<O3>"),
     ("conv3d", dict(VEC=4, TX=64, TY=4, ROWS=16, NTL=1), "default<O3>"),
     ("conv3d", dict(VEC=2, TX=64, TY=4, YR=4, ROWS=16, USE_LDS=2, ORDER=1, NTL=1), "default<O3>"),
@@ -215,7 +218,7 @@ def check(ctx, family):
             out = h(ctx.conv3d(g(vol), taps, out=torch.full((D, H, W), float("nan"), device=DEV)))
             assert o.max_err(out, o.conv3d(vol, taps), o.conv3d(np.abs(vol), np.abs(taps))) <= 1e-4
     elif family == "colstats":
-        for n, m in ((130, 70), (1000, 257), (2, 5)):
+        for n, m in ((130, 70), (1000, 257), (2, 5), (2100, 130)):
             X, eps = synth.corr_inputs(n, m)
             mu, sd = ctx.colstats(g(X), eps)
             mr, sr = o.colstats(X, eps)

@@ -223,6 +223,14 @@ def check(ctx, family):
             mu, sd = ctx.colstats(g(X), eps)
             mr, sr = o.colstats(X, eps)
             assert o.max_err(h(mu), mr, o.colstats(np.abs(X), eps)[0]) <= 1e-6 and o.max_err(h(sd), sr) <= 1e-5
+        # deviations of about 1 on an offset of 1e4 (the bar of the default's shift test)
+        X, eps = synth.corr_inputs(1000, 70)
+        X = (X - X.mean(axis=0) + 1e4).astype(np.float32)
+        X[:, 3] = 7.25                                   # a constant column: deviation floored
+        mu, sd = ctx.colstats(g(X), eps)
+        mr, sr = o.colstats(X, eps)
+        assert o.max_err(h(mu), mr, o.colstats(np.abs(X), eps)[0]) <= 1e-6 and o.max_err(h(sd), sr) <= 1e-4
+        assert h(sd)[3] == np.float32(eps)
     elif family == "gesummv":
         for N in (1, 130, 1000, 4097):
             A, B, x = synth.uniform(871, (N, N)), synth.uniform(872, (N, N)), synth.uniform(873, (N,))

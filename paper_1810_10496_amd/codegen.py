@@ -54,7 +54,8 @@ def _fs(name, fid, src, fixed, defaults, op, prec="fp32"):
 
 FAMILIES = {f.name: f for f in [
     _fs("gemm_f32", 0, "gemm.hip", {"PREC": 0},
-        dict(BM=128, BN=128, BK=16, WAVES_M=2, WAVES_N=2, VEC=4, UNROLL=1, USE_LDS=1, ORDER=3, MF=16, LDS_PAD=4, FC=0, IL=0),
+        dict(BM=128, BN=128, BK=16, WAVES_M=2, WAVES_N=2, VEC=4, UNROLL=1, USE_LDS=1, ORDER=3, MF=16, LDS_PAD=4, FC=0, IL=0,
+             DK=0),
         "gemm"),
     _fs("gemm_bf16", 1, "gemm_lp.hip", {"PREC": 1},
         dict(BM=256, BN=128, BK=32, WAVES_M=4, WAVES_N=2, VEC=4, STAGES=2, ORDER=3), "gemm", "bf16"),

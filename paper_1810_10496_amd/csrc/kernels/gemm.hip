@@ -67,6 +67,9 @@
 #ifndef IL           // FP32, two LDS stages: 1 = full interior tiles run a branch-free k loop whose
 #define IL 0         // LDS stores and global loads are interleaved with the MFMAs (below)
 #endif
+#ifndef DK           // FP32 without LDS: 1 = branch-free fragment loads (address clamped into the
+#define DK 0         // matrix, value zeroed outside it), so an unrolled k loop is straight-line
+#endif               // code whose loads can all be issued ahead of the MFMAs
 
 #define FAMILY ((PREC) == 0 ? PKF_GEMM_F32 : ((PREC) == 1 ? PKF_GEMM_BF16 : PKF_GEMM_SPLIT))
 
@@ -85,6 +88,7 @@ static_assert(WTM % BLK == 0 && WTN % BLK == 0, "wave tile must be a multiple of
 static_assert(PREC != 0 || STEPS % 4 == 0, "FP32 fragments are read four k at a time");
 static_assert(FC == 0 || (FC == 4 && PREC == 0 && STEPS % FC == 0), "FC is 0, or 4 for FP32");
 static_assert(IL == 0 || (PREC == 0 && USE_LDS == 2 && FC == 0), "IL: FP32 with two LDS stages");
+static_assert(DK == 0 || (PREC == 0 && USE_LDS == 0 && MF == 16), "DK: FP32 without LDS, 16x16 blocks");
 static_assert(BK % KI == 0 && BK % VEC == 0, "bad BK");
 static_assert(VEC == 1 || VEC == 2 || VEC == 4, "bad VEC");
 static_assert(BN % VEC == 0, "bad BN");
@@ -302,9 +306,21 @@ __device__ __forceinline__ void read_frag4(const lds_t *S, int row, int g, int s
 __device__ __forceinline__ void global_frag_a(const pk_gemm_args &a, int64_t row, int64_t kbase,
                                               frag_t *f, frag_t *f2) {
     float t[KG];
+#if DK
+    // the value is masked with an AND (a select would let the compiler move the load
+    // under a branch on the condition, where each load waits for itself)
+    const int64_t rc = min(row, a.M - 1);
+#pragma unroll
+    for (int e = 0; e < KG; ++e) {
+        const float v = a.A[rc * a.lda + min(kbase + e, a.K - 1)];
+        const uint32_t keep = 0u - (uint32_t)((row < a.M) & (kbase + e < a.K));
+        t[e] = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v) & keep);
+    }
+#else
 #pragma unroll
     for (int e = 0; e < KG; ++e)
         t[e] = (row < a.M && kbase + e < a.K) ? a.A[row * a.lda + kbase + e] : 0.f;
+#endif
 #if PREC == 0
 #pragma unroll
     for (int s = 0; s < STEPS; ++s)
@@ -335,9 +351,19 @@ __device__ __forceinline__ void global_frag_a(const pk_gemm_args &a, int64_t row
 __device__ __forceinline__ void global_frag_b(const pk_gemm_args &a, int64_t col, int64_t kbase,
                                               frag_t *f, frag_t *f2) {
     float t[KG];
+#if DK
+    const int64_t cc = min(col, a.N - 1);
+#pragma unroll
+    for (int e = 0; e < KG; ++e) {
+        const float v = a.B[min(kbase + e, a.K - 1) * a.ldb + cc];
+        const uint32_t keep = 0u - (uint32_t)((col < a.N) & (kbase + e < a.K));
+        t[e] = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v) & keep);
+    }
+#else
 #pragma unroll
     for (int e = 0; e < KG; ++e)
         t[e] = (col < a.N && kbase + e < a.K) ? a.B[(kbase + e) * a.ldb + col] : 0.f;
+#endif
 #if PREC == 0
 #pragma unroll
     for (int s = 0; s < STEPS; ++s)
@@ -457,6 +483,61 @@ __device__ __forceinline__ void il_main(const pk_gemm_args &a, float *lds, int r
         __builtin_amdgcn_sched_group_barrier(0x008, IL_REST, 0);
         __syncthreads();
     }
+}
+#endif
+
+#if DK
+// one group of UNROLL k tiles starting at k0, read straight from memory into fragments
+// (rows r0 + i*BLK of A, columns c0 + j*BLK of B for this lane), then the MFMAs
+template <bool INK>
+__device__ __forceinline__ void dk_group(const pk_gemm_args &a, int64_t k0, int64_t r0, int64_t c0, int g,
+                                         acc_t (&acc)[FM][FN]) {
+    constexpr int NLD = UNROLL * (FM + FN) * KG;     // loads of the group
+    float ta[UNROLL][FM][KG], tb[UNROLL][FN][KG];
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+        const int64_t r = r0 + i * BLK;
+        const float *pa = a.A + min(r, a.M - 1) * a.lda;
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u)
+#pragma unroll
+            for (int e = 0; e < KG; ++e) {
+                const int64_t k = k0 + u * BK + g * KG + e;
+                ta[u][i][e] = pa[INK ? k : min(k, a.K - 1)];
+            }
+    }
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+        const int64_t c = min(c0 + j * BLK, a.N - 1);
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u)
+#pragma unroll
+            for (int e = 0; e < KG; ++e) {
+                const int64_t k = k0 + u * BK + g * KG + e;
+                tb[u][j][e] = a.B[(INK ? k : min(k, a.K - 1)) * a.ldb + c];
+            }
+    }
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u)
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s)
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j) {
+                    // masks by AND: a select on a loaded value can be turned into a
+                    // branch around the load, where each load waits for itself
+                    const int64_t k = k0 + u * BK + g * KG + s;
+                    const uint32_t kin = INK ? 1u : (uint32_t)(k < a.K);
+                    const uint32_t mx = 0u - (kin & (uint32_t)(r0 + i * BLK < a.M));
+                    const uint32_t my = 0u - (kin & (uint32_t)(c0 + j * BLK < a.N));
+                    const float x = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, ta[u][i][s]) & mx);
+                    const float y = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, tb[u][j][s]) & my);
+                    acc[i][j] = mma(x, y, acc[i][j]);
+                }
+    // the groups take their members from the code above: all of the loads, then the MFMAs
+    __builtin_amdgcn_sched_group_barrier(0x020, NLD, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, UNROLL * STEPS * FM * FN, 0);
 }
 #endif
 
@@ -665,6 +746,19 @@ __device__ __forceinline__ void gemm_body(const pk_gemm_args &a, lds_t *lds) {
     }
 #endif
 #else
+#if DK
+    // k tiles in groups of UNROLL: every fragment of a group is loaded into registers
+    // first (a scheduling-group barrier keeps all those loads ahead of the rest, in
+    // flight together), then the group's MFMAs run.  A group inside K reads its rows
+    // and columns at constant offsets; the last group, if it reaches past K, reads
+    // clamped addresses masked to zero in both operands (exact zeros).
+    for (int64_t ku = 0; ku < (nk + UNROLL - 1) / UNROLL; ++ku) {
+        if ((ku + 1) * UNROLL * BK <= a.K)
+            dk_group<true>(a, ku * UNROLL * BK, row0 + wm * WTM + lr, col0 + wn * WTN + lr, g, acc);
+        else
+            dk_group<false>(a, ku * UNROLL * BK, row0 + wm * WTM + lr, col0 + wn * WTN + lr, g, acc);
+    }
+#else
 #pragma unroll UNROLL
     for (int64_t kt = 0; kt < nk; ++kt) {
         const int64_t kbase = kt * BK + g * KG;
@@ -689,6 +783,7 @@ __device__ __forceinline__ void gemm_body(const pk_gemm_args &a, lds_t *lds) {
                     acc[i][j] = mma(fa[i][s], fb[j][s], acc[i][j]);
                 }
     }
+#endif
     (void)V;
 #endif
 #if IL

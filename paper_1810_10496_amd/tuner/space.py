@@ -48,7 +48,7 @@ DOMAINS = {
 #   read in chunks of four k (deep k-steps; BK 64, also refine-only, may use the whole LDS);
 #   IL: the interleaved k loop of full interior tiles (two LDS stages)
 REFINE_ONLY = {
-    "gemm_f32": dict(MF=[16, 32], LDS_PAD=[4, 8], FC=[0, 4], IL=[0, 1]),
+    "gemm_f32": dict(MF=[16, 32], LDS_PAD=[4, 8], FC=[0, 4], IL=[0, 1], DK=[0, 1]),
     "gemv": dict(NTL=[0, 1]),
     "gemv_t": dict(FUSE=[0, 1], NTL=[0, 1]),
     "gemv_pair": dict(FUSE=[0, 1], NTL=[0, 1]),
@@ -156,6 +156,10 @@ def valid(family: str, k: dict) -> bool:
         lds = stages * (k["BM"] + k["BN"]) * (k["BK"] + k.get("LDS_PAD", 4)) * 4 if k["USE_LDS"] else 0
         if k.get("FC", 0) and ((k["BK"] // (64 // blk)) % 4 or blk != 16 and blk != 32):
             return False
+        if k.get("DK", 0) and k["USE_LDS"] != 0:
+            return False
+        if k["UNROLL"] > 2 and not k.get("DK", 0):
+            return False                     # deep unrolls only for the branch-free direct loads
         if k.get("IL", 0):
             nt = 64 * k["WAVES_M"] * k["WAVES_N"]
             if (k["USE_LDS"] != 2 or k.get("FC", 0) or k["VEC"] != 4 or (k["BM"] * k["BK"] // 4) % nt

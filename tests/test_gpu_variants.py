@@ -47,6 +47,14 @@ VARIANTS = [
     ("gemm_f32", dict(BM=128, BN=256, BK=64, WAVES_M=2, WAVES_N=4, VEC=4, USE_LDS=1, ORDER=3, FC=4, MF=32,
                       LDS_PAD=8), "default<O3>"),
     ("gemm_f32", dict(BM=256, BN=128, BK=32, WAVES_M=4, WAVES_N=2, VEC=2, USE_LDS=1, ORDER=0, FC=4), "default<O3>"),
+    # fragments loaded straight from memory without branches, k tiles in groups of 2-8
+    # (a group inside K, and a last group reaching past it: clamped and masked)
+    ("gemm_f32", dict(BM=16, BN=16, BK=32, WAVES_M=1, WAVES_N=1, VEC=4, USE_LDS=0, ORDER=3, DK=1, UNROLL=8),
+     "default<O3>"),
+    ("gemm_f32", dict(BM=32, BN=32, BK=16, WAVES_M=2, WAVES_N=2, VEC=4, USE_LDS=0, ORDER=3, DK=1, UNROLL=4),
+     "default<O3>"),
+    ("gemm_f32", dict(BM=64, BN=32, BK=32, WAVES_M=2, WAVES_N=1, VEC=4, USE_LDS=0, ORDER=0, DK=1, UNROLL=2),
+     "default<O3>"),
     # the interleaved k loop of full tiles (edge tiles and ragged K take the general loop)
     ("gemm_f32", dict(BM=128, BN=128, BK=32, WAVES_M=2, WAVES_N=2, VEC=4, USE_LDS=2, ORDER=3, IL=1), "default<O3>"),
     ("gemm_f32", dict(BM=256, BN=128, BK=16, WAVES_M=4, WAVES_N=2, VEC=4, USE_LDS=2, ORDER=3, IL=1, LDS_PAD=8),

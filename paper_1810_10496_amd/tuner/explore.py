@@ -375,6 +375,15 @@ def _gemm32_grid():
                     for mf in (16, 32):
                         out.append(dict(BM=bm, BN=bn, WAVES_M=wm, WAVES_N=wn, BK=bk, USE_LDS=2, LDS_PAD=pad,
                                         MF=mf, FC=0, IL=1, VEC=4, UNROLL=1, ORDER=3))
+    # small problems with full tiles: the interleaved loop with 32- and 64-wide tiles and
+    # k steps up to 128 deep (a 256-deep product in two to eight steps)
+    for bm in (32, 64):
+        for bn in (32, 64):
+            for wm, wn in ((1, 1), (2, 1), (1, 2), (2, 2)):
+                for bk in (32, 64, 128):
+                    for pad in (4, 8):
+                        out.append(dict(BM=bm, BN=bn, WAVES_M=wm, WAVES_N=wn, BK=bk, USE_LDS=2, LDS_PAD=pad,
+                                        MF=16, FC=0, IL=1, VEC=4, UNROLL=1, ORDER=3))
     # small problems: fragments loaded straight from memory without branches (DK), the k
     # loop unrolled 2-8 deep so that several k tiles' loads are in flight at once
     for bm in (16, 32, 64):

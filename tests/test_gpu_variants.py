@@ -63,6 +63,8 @@ VARIANTS = [
                       LDS_PAD=8), "default<O3>"),
     ("gemm_f32", dict(BM=256, BN=256, BK=16, WAVES_M=2, WAVES_N=2, VEC=4, USE_LDS=2, ORDER=2, IL=1, MF=32),
      "default<O3>"),
+    ("gemm_f32", dict(BM=32, BN=32, BK=128, WAVES_M=2, WAVES_N=2, VEC=4, USE_LDS=2, ORDER=3, IL=1, LDS_PAD=8),
+     "default<O3>"),
     ("gemv", dict(ROWS=4, WAVES=2, VEC=2, UNROLL=8, USE_LDS=1), "default<O3>"),
     ("gemv_t", dict(ROWS=128, WAVES=8, VEC=1, UNROLL=8, ORDER=1), "default<O2>"),
     ("gemv_pair", dict(ROWS=256, WAVES=1, VEC=2, UNROLL=32, ORDER=1), "default<O3>"),

@@ -65,8 +65,8 @@
 #define FC 0         // time, each chunk's MFMAs right after it (deep k-steps in fewer registers)
 #endif
 #ifndef IL           // FP32, two LDS stages: 1 = full interior tiles run a branch-free k loop whose
-#define IL 0         // LDS stores and global loads are interleaved with the MFMAs (below)
-#endif
+#define IL 0         // LDS stores and global loads are interleaved with the MFMAs (below); 2 = the
+#endif               // same for K any multiple of 4 (the partial last k tile masked)
 #ifndef DK           // FP32 without LDS: 1 = branch-free fragment loads (address clamped into the
 #define DK 0         // matrix, value zeroed outside it), so an unrolled k loop is straight-line
 #endif               // code whose loads can all be issued ahead of the MFMAs
@@ -412,6 +412,24 @@ constexpr int IL_REST = IL_MMA - IL_DSW * IL_MW - IL_VMR * IL_MV;
 
 __device__ __forceinline__ void il_load(const pk_gemm_args &a, int row0, int col0, int64_t k0, int tid,
                                         f32x4 *ra, f32x4 *rb) {
+#if IL == 2
+    // K a multiple of 4, the last k tile partial: a chunk past K reads the last one in
+    // the row (A) or the last row (B) and is masked to zeros with an AND (no branch)
+#pragma unroll
+    for (int p = 0; p < IL_PA; ++p) {
+        const int q = p * NT + tid;
+        const int64_t k = k0 + (q % (BK / 4)) * 4;
+        const f32x4 v = *reinterpret_cast<const f32x4 *>(a.A + (int64_t)(row0 + q / (BK / 4)) * a.lda + min(k, a.K - 4));
+        ra[p] = __builtin_bit_cast(f32x4, __builtin_bit_cast(u32x4, v) & (0u - (uint32_t)(k < a.K)));
+    }
+#pragma unroll
+    for (int p = 0; p < IL_PB; ++p) {
+        const int q = p * NT + tid;
+        const int64_t k = k0 + q % BK;
+        const f32x4 v = *reinterpret_cast<const f32x4 *>(a.B + min(k, a.K - 1) * a.ldb + col0 + (q / BK) * 4);
+        rb[p] = __builtin_bit_cast(f32x4, __builtin_bit_cast(u32x4, v) & (0u - (uint32_t)(k < a.K)));
+    }
+#else
 #pragma unroll
     for (int p = 0; p < IL_PA; ++p) {
         const int q = p * NT + tid;
@@ -422,6 +440,7 @@ __device__ __forceinline__ void il_load(const pk_gemm_args &a, int row0, int col
         const int q = p * NT + tid;
         rb[p] = *reinterpret_cast<const f32x4 *>(a.B + (k0 + q % BK) * a.ldb + col0 + (q / BK) * 4);
     }
+#endif
 }
 
 __device__ __forceinline__ void il_store(float *As, float *Bs, int tid, const f32x4 *ra, const f32x4 *rb) {
@@ -443,7 +462,11 @@ __device__ __forceinline__ void il_store(float *As, float *Bs, int tid, const f3
 __device__ __forceinline__ void il_main(const pk_gemm_args &a, float *lds, int row0, int col0, int tid, int wm,
                                         int wn, int g, int lr, acc_t (&acc)[FM][FN]) {
     constexpr int STAGE = (BM + BN) * LDK;
+#if IL == 2
+    const int64_t nk = (a.K + BK - 1) / BK;
+#else
     const int64_t nk = a.K / BK;
+#endif
     f32x4 ra[IL_PA], rb[IL_PB];
     il_load(a, row0, col0, 0, tid, ra, rb);
     il_store(lds, lds + BM * LDK, tid, ra, rb);
@@ -579,7 +602,11 @@ __device__ __forceinline__ void gemm_body(const pk_gemm_args &a, lds_t *lds) {
     const int64_t nk = (a.K + BK - 1) / BK;
 
 #if IL
+#if IL == 2
+    if (row0 + BM <= a.M && col0 + BN <= a.N && a.K % 4 == 0 && nk >= 2 && a.aligned && V == 4) {
+#else
     if (row0 + BM <= a.M && col0 + BN <= a.N && a.K % BK == 0 && nk >= 2 && a.aligned && V == 4) {
+#endif
         il_main(a, lds, row0, col0, tid, wm, wn, g, lr, acc);
     } else {
 #endif

@@ -384,6 +384,13 @@ def _gemm32_grid():
                     for pad in (4, 8):
                         out.append(dict(BM=bm, BN=bn, WAVES_M=wm, WAVES_N=wn, BK=bk, USE_LDS=2, LDS_PAD=pad,
                                         MF=16, FC=0, IL=1, VEC=4, UNROLL=1, ORDER=3))
+    # K not a multiple of the k step (a masked last tile): 32-128-wide tiles
+    for bm in (32, 64, 128):
+        for bn in (32, 64, 128):
+            for wm, wn in ((1, 1), (2, 1), (1, 2), (2, 2), (2, 4), (4, 2)):
+                for bk in (32, 64):
+                    out.append(dict(BM=bm, BN=bn, WAVES_M=wm, WAVES_N=wn, BK=bk, USE_LDS=2, LDS_PAD=8,
+                                    MF=16, FC=0, IL=2, VEC=4, UNROLL=1, ORDER=3))
     # small problems: fragments loaded straight from memory without branches (DK), the k
     # loop unrolled 2-8 deep so that several k tiles' loads are in flight at once
     for bm in (16, 32, 64):

@@ -48,7 +48,7 @@ DOMAINS = {
 #   read in chunks of four k (deep k-steps; BK 64, also refine-only, may use the whole LDS);
 #   IL: the interleaved k loop of full interior tiles (two LDS stages)
 REFINE_ONLY = {
-    "gemm_f32": dict(MF=[16, 32], LDS_PAD=[4, 8], FC=[0, 4], IL=[0, 1], DK=[0, 1]),
+    "gemm_f32": dict(MF=[16, 32], LDS_PAD=[4, 8], FC=[0, 4], IL=[0, 1, 2], DK=[0, 1]),
     "gemv": dict(NTL=[0, 1]),
     "gemv_t": dict(FUSE=[0, 1], NTL=[0, 1]),
     "gemv_pair": dict(FUSE=[0, 1], NTL=[0, 1]),

@@ -65,6 +65,11 @@ VARIANTS = [
      "default<O3>"),
     ("gemm_f32", dict(BM=32, BN=32, BK=128, WAVES_M=2, WAVES_N=2, VEC=4, USE_LDS=2, ORDER=3, IL=1, LDS_PAD=8),
      "default<O3>"),
+    # ... with a masked partial last k tile (K a multiple of 4)
+    ("gemm_f32", dict(BM=64, BN=64, BK=64, WAVES_M=2, WAVES_N=2, VEC=4, USE_LDS=2, ORDER=3, IL=2, LDS_PAD=8),
+     "default<O3>"),
+    ("gemm_f32", dict(BM=32, BN=64, BK=32, WAVES_M=1, WAVES_N=2, VEC=4, USE_LDS=2, ORDER=3, IL=2, LDS_PAD=8),
+     "default<O3>"),
     ("gemv", dict(ROWS=4, WAVES=2, VEC=2, UNROLL=8, USE_LDS=1), "default<O3>"),
     ("gemv_t", dict(ROWS=128, WAVES=8, VEC=1, UNROLL=8, ORDER=1), "default<O2>"),
     ("gemv_pair", dict(ROWS=256, WAVES=1, VEC=2, UNROLL=32, ORDER=1), "default<O3>"),
@@ -188,7 +193,7 @@ def check(ctx, family):
     """Run the family's operation on ragged shapes and compare with the oracle."""
     if family == "gemm_f32":
         # ragged shapes, and shapes with full interior tiles and K a multiple of every k step
-        for M, N, K in ((65, 33, 47), (200, 130, 257), (1, 1, 1), (300, 260, 96), (256, 256, 512)):
+        for M, N, K in ((65, 33, 47), (200, 130, 257), (1, 1, 1), (300, 260, 96), (256, 256, 512), (192, 256, 100)):
             A, B, C, a, b = synth.gemm_inputs(N, m=M, k=K)
             Cg = g(C)
             ctx.gemm(g(A), g(B), Cg, a, b)

@@ -44,8 +44,8 @@
 #define ORDER 0
 #endif
 #ifndef IL           // two stages: 1 = full tiles run a branch-free k loop whose LDS stores and
-#define IL 0         // global loads are interleaved with the MFMAs (below)
-#endif
+#define IL 0         // global loads are interleaved with the MFMAs (below); 2 = the same for any
+#endif               // n (samples past n read the last one and are zeroed)
 
 constexpr int NT = 64 * WAVES_M * WAVES_N;
 constexpr int WTM = BT / WAVES_M;
@@ -164,10 +164,29 @@ __device__ __forceinline__ void il_load(const pk_syrk_args &a, int64_t col0, int
 #pragma unroll
     for (int p = 0; p < IL_P; ++p) {
         const int q = p * NT + tid;
+#if IL == 2
+        // a sample past n reads the last one (its normalised value is zeroed at the store)
+        r[p] = *reinterpret_cast<const f32x4 *>(a.X + min(i0 + q / (BT / 4), a.n - 1) * a.ldx + col0 +
+                                                (q % (BT / 4)) * 4);
+#else
         r[p] = *reinterpret_cast<const f32x4 *>(a.X + (i0 + q / (BT / 4)) * a.ldx + col0 + (q % (BT / 4)) * 4);
+#endif
     }
 }
 
+#if IL == 2
+__device__ __forceinline__ void il_store(float *S, int tid, const f32x4 *r, const f32x4 *mu, const f32x4 *rs,
+                                         int64_t i0, int64_t n) {
+#pragma unroll
+    for (int p = 0; p < IL_P; ++p) {
+        const int q = p * NT + tid;
+        const f32x4 z = (r[p] - mu[p]) * rs[p];
+        const uint32_t keep = 0u - (uint32_t)(i0 + q / (BT / 4) < n);     // samples past n add zeros
+        *reinterpret_cast<f32x4 *>(S + (q / (BT / 4)) * LDR + (q % (BT / 4)) * 4) =
+            __builtin_bit_cast(f32x4, __builtin_bit_cast(u32x4, z) & keep);
+    }
+}
+#else
 __device__ __forceinline__ void il_store(float *S, int tid, const f32x4 *r, const f32x4 *mu, const f32x4 *rs) {
 #pragma unroll
     for (int p = 0; p < IL_P; ++p) {
@@ -175,6 +194,13 @@ __device__ __forceinline__ void il_store(float *S, int tid, const f32x4 *r, cons
         *reinterpret_cast<f32x4 *>(S + (q / (BT / 4)) * LDR + (q % (BT / 4)) * 4) = (r[p] - mu[p]) * rs[p];
     }
 }
+#endif
+
+#if IL == 2
+#define IL_STORE(S, r, mu, rs, i0) il_store(S, tid, r, mu, rs, i0, a.n)
+#else
+#define IL_STORE(S, r, mu, rs, i0) il_store(S, tid, r, mu, rs)
+#endif
 
 template <bool DIAG>
 __device__ __forceinline__ void il_main(const pk_syrk_args &a, float *lds, int64_t j0, int64_t k0, int tid,
@@ -196,14 +222,18 @@ __device__ __forceinline__ void il_main(const pk_syrk_args &a, float *lds, int64
         muk[p] = f32x4{stat[2][c], stat[2][c + 1], stat[2][c + 2], stat[2][c + 3]};
         rsk[p] = f32x4{stat[3][c], stat[3][c + 1], stat[3][c + 2], stat[3][c + 3]};
     }
+#if IL == 2
+    const int64_t nk = (a.n + BK - 1) / BK;
+#else
     const int64_t nk = a.n / BK;
+#endif
     f32x4 rj[IL_P], rk[IL_P];
     il_load(a, j0, 0, tid, rj);
     if (!DIAG)
         il_load(a, k0, 0, tid, rk);
-    il_store(lds, tid, rj, muj, rsj);
+    IL_STORE(lds, rj, muj, rsj, 0);
     if (!DIAG)
-        il_store(lds + TILE, tid, rk, muk, rsk);
+        IL_STORE(lds + TILE, rk, muk, rsk, 0);
     il_load(a, j0, BK, tid, rj);
     if (!DIAG)
         il_load(a, k0, BK, tid, rk);
@@ -229,9 +259,9 @@ __device__ __forceinline__ void il_main(const pk_syrk_args &a, float *lds, int64
 #pragma unroll
                 for (int j = 0; j < FN; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[s][i], fb[s][j], acc[i][j], 0, 0, 0);
-        il_store(Nj, tid, rj, muj, rsj);                         // tile kt+1
+        IL_STORE(Nj, rj, muj, rsj, (kt + 1) * BK);               // tile kt+1
         if (!DIAG)
-            il_store(Nk, tid, rk, muk, rsk);
+            IL_STORE(Nk, rk, muk, rsk, (kt + 1) * BK);
         const int64_t i2 = min(kt + 2, nk - 1) * BK;             // tile kt+2
         il_load(a, j0, i2, tid, rj);
         if (!DIAG)
@@ -292,7 +322,11 @@ __device__ __forceinline__ void syrk32_body(const pk_syrk_args &a, float *lds, f
             acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
 #if IL
+#if IL == 2
+    if (j0 + BT <= a.m && k0 + BT <= a.m && a.n > BK && a.aligned && V == 4) {
+#else
     if (j0 + BT <= a.m && k0 + BT <= a.m && a.n % BK == 0 && a.n >= 2 * BK && a.aligned && V == 4) {
+#endif
         if (diag)
             il_main<true>(a, lds, j0, k0, tid, wm, wn, g, l16, stat, acc);
         else

@@ -345,11 +345,12 @@ def _stencil_grids():
 
 def _syrk32_grid():
     """The FP32 rank-k product of the correlation with the interleaved k loop of full
-    tiles (IL): 32-128-wide triangle tiles, 1-16 wavefronts, k steps 16-128 deep (the deep
-    ones for small sample counts: a 256-sample problem in two to four steps), the
-    row-order and the XCD-aware rasters."""
-    return [dict(BT=bt, BK=bk, WAVES_M=wm, WAVES_N=wn, VEC=4, STAGES=2, ORDER=order, IL=1)
-            for bt in (32, 64, 96, 128) for bk in (16, 32, 64, 128)
+    tiles (IL; IL = 2 for sample counts that are not a multiple of the step): 32-128-wide
+    triangle tiles, 1-16 wavefronts, k steps 16-128 deep (the deep ones for small sample
+    counts: a 256-sample problem in two to four steps), the row-order and the XCD-aware
+    rasters."""
+    return [dict(BT=bt, BK=bk, WAVES_M=wm, WAVES_N=wn, VEC=4, STAGES=2, ORDER=order, IL=il)
+            for il in (1, 2) for bt in (32, 64, 96, 128) for bk in (16, 32, 64, 128)
             for wm, wn in ((1, 1), (1, 2), (2, 1), (2, 2), (2, 4), (4, 2), (4, 4)) for order in (0, 2)]
 
 

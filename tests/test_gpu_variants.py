@@ -107,6 +107,8 @@ VARIANTS = [
     ("syrk_f32", dict(BT=96, BK=16, WAVES_M=2, WAVES_N=1, VEC=4, STAGES=2, ORDER=0, IL=1), "default<O3>"),
     ("syrk_f32", dict(BT=128, BK=32, WAVES_M=2, WAVES_N=4, VEC=4, STAGES=2, ORDER=2, IL=1), "default<O3>"),
     ("syrk_f32", dict(BT=32, BK=128, WAVES_M=2, WAVES_N=2, VEC=4, STAGES=2, ORDER=0, IL=1), "default<O3>"),
+    ("syrk_f32", dict(BT=32, BK=64, WAVES_M=2, WAVES_N=2, VEC=4, STAGES=2, ORDER=0, IL=2), "default<O3>"),
+    ("syrk_f32", dict(BT=64, BK=16, WAVES_M=2, WAVES_N=2, VEC=4, STAGES=2, ORDER=2, IL=2), "default<O3>"),
     ("conv2d", dict(VEC=4, TX=64, TY=4, ROWS=4, ORDER=2), "default<O3>"),
     # the bf16 / split-bf16 GEMM kernel: tile shapes, one and two LDS stages, scalar loads
     ("gemm_bf16", dict(BM=128, BN=128, BK=64, WAVES_M=2, WAVES_N=2, VEC=4, STAGES=2, ORDER=0), "default<O3>"),
@@ -256,7 +258,7 @@ def check(ctx, family):
     elif family in ("syrk_f32", "syrk_bf16", "syrk_split"):
         prec = {"syrk_f32": "fp32", "syrk_bf16": "bf16", "syrk_split": "split"}[family]
         tol = {"fp32": 1e-4, "bf16": 2e-2, "split": 1e-5}[prec]
-        for n, m in ((257, 129), (130, 70), (2, 3), (300, 200), (512, 384)):
+        for n, m in ((257, 129), (130, 70), (2, 3), (300, 200), (512, 384), (1000, 256)):
             X, eps = synth.corr_inputs(n, m)
             R, _, _ = ctx.corr(g(X), eps, prec=prec)
             Rr, S = o.corr(X, eps, with_scale=True)

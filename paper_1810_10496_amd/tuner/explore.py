@@ -319,7 +319,9 @@ ONE_LAUNCH_GRID = {
     "gemv_pair": [dict(ROWS=r, WAVES=w, VEC=v, UNROLL=u, ORDER=0, FUSE=1) for r in (128, 256, 512)
                   for w in (4, 8) for v in (1, 2, 4) for u in (4, 8, 16)],
     "colstats": [dict(VEC=v, WAVES=w, ROWS=r, ORDER=0, FUSE=1) for v in (1, 2, 4) for w in (4, 8)
-                 for r in (128, 256, 512)],
+                 for r in (128, 256, 512)]
+                + [dict(VEC=v, WAVES=w, ROWS=r, ORDER=o, NTL=ntl, MG=1) for v in (1, 2, 4) for w in (4, 8)
+                   for r in (16, 32, 64, 128) for o in (0, 1) for ntl in (0, 1)],   # the one-pass merge
 }
 
 

@@ -121,10 +121,9 @@ def main(argv=None):
         for fam in fams:
             if fam not in X.REFINE_GRIDS:
                 continue
-            tag = "one-launch grid" if fam in X.ONE_LAUNCH_GRID else "structured grid"
             only = dict((k, int(v)) for k, v in (o.split("=", 1) for o in a.only))
             grid = [g for g in X.REFINE_GRIDS[fam] if all(g.get(k) == v for k, v in only.items())]
-            n = X.refine(fam, a.workdir, path, grid, sizes, log=log, tag=tag, jobs=a.jobs)
+            n = X.refine(fam, a.workdir, path, grid, sizes, log=log, tag="structured grid", jobs=a.jobs)
             log(f"[refine] {fam}: {n} entries replaced")
         return 0
 

@@ -315,9 +315,15 @@ def finalize(family, workdir, sizes=(256, 512, 1000, 2048, 4096), top=10, replay
 # group folding the partials; the grid `refine` adds to a table measured without them
 ONE_LAUNCH_GRID = {
     "gemv_t": [dict(ROWS=r, WAVES=w, VEC=v, UNROLL=u, ORDER=0, FUSE=1) for r in (128, 256, 512)
-               for w in (4, 8) for v in (1, 2, 4) for u in (4, 8, 16)],
+               for w in (4, 8) for v in (1, 2, 4) for u in (4, 8, 16)]
+              + [dict(ROWS=r, WAVES=w, VEC=v, UNROLL=16, ORDER=o, NTL=1) for r in (16, 32, 64, 128)
+                 for w in (2, 4, 8) for v in (1, 2, 4) for o in (0, 1)],     # non-temporal, two launches
     "gemv_pair": [dict(ROWS=r, WAVES=w, VEC=v, UNROLL=u, ORDER=0, FUSE=1) for r in (128, 256, 512)
-                  for w in (4, 8) for v in (1, 2, 4) for u in (4, 8, 16)],
+                  for w in (4, 8) for v in (1, 2, 4) for u in (4, 8, 16)]
+                 + [dict(ROWS=r, WAVES=w, VEC=v, UNROLL=16, ORDER=o, NTL=1) for r in (16, 32, 64, 128)
+                    for w in (2, 4, 8) for v in (1, 2, 4) for o in (0, 1)],
+    "gemv": [dict(ROWS=r, WAVES=w, VEC=4, UNROLL=u, USE_LDS=l, ORDER=0, NTL=1) for r in (1, 2, 4)
+             for w in (2, 4, 8) for u in (1, 2, 4) for l in (0, 1)],
     "colstats": [dict(VEC=v, WAVES=w, ROWS=r, ORDER=0, FUSE=1) for v in (1, 2, 4) for w in (4, 8)
                  for r in (128, 256, 512)]
                 + [dict(VEC=v, WAVES=w, ROWS=r, ORDER=o, NTL=ntl, MG=1) for v in (1, 2, 4) for w in (4, 8)
@@ -486,7 +492,7 @@ def refine(family, workdir, table_path, grid, sizes=(256, 512, 1000, 2048, 4096)
             entries[idx[0]] = dict(family=family, bucket=bucket, size=size, is_default=False, knobs=v.knobs,
                                    pipeline=v.pipeline, llc_flags=list(v.llc_flags), opt_flags=list(v.opt_flags),
                                    code_sha256=sha, default_ms=t_def, tuned_ms=t, speedup=t_def / t,
-                                   source=tag)
+                                   source="one-launch grid" if v.knobs.get("FUSE", 0) else tag)
             changed += 1
     finally:
         ev.close()

@@ -45,7 +45,8 @@
 #endif
 #ifndef IL           // two stages: 1 = full tiles run a branch-free k loop whose LDS stores and
 #define IL 0         // global loads are interleaved with the MFMAs (below); 2 = the same for any
-#endif               // n (samples past n read the last one and are zeroed)
+#endif               // n (samples past n read the last one and are zeroed); 3 = as 1, with the
+                     // column statistics kept in the second stage (less LDS per block)
 
 constexpr int NT = 64 * WAVES_M * WAVES_N;
 constexpr int WTM = BT / WAVES_M;
@@ -62,10 +63,12 @@ static_assert(BK % 4 == 0, "BK must be a multiple of 4");
 static_assert(BT % VEC == 0, "bad VEC");
 static_assert(STAGES == 1 || STAGES == 2, "bad STAGES");
 static_assert(IL == 0 || (STAGES == 2 && (BK * BT / 4) % NT == 0), "IL: two stages, whole chunks per thread");
+// the general loop's stages: one when the statistics live in the second stage (IL 3)
+constexpr int GST = IL == 3 ? 1 : STAGES;
 
 // knob slot X2 records 1, + 1000 with IL
 PK_DEFINE_KNOBS(PKF_SYRK_F32, BT, BT, BK, WAVES_M, WAVES_N, VEC, 1, STAGES, ORDER, 0, 1 + 1000 * IL, NT,
-                LDS_FLOATS * 4 + 4 * BT * 4, PK_KERNEL_ABI_VERSION, 0)
+                LDS_FLOATS * 4 + (IL == 3 ? 0 : 4 * BT * 4), PK_KERNEL_ABI_VERSION, 0)
 
 // block index -> lower-triangle tile (bj >= bk)
 __device__ __forceinline__ void tri_tile(int b, int nt, int &bj, int &bk) {
@@ -338,7 +341,7 @@ __device__ __forceinline__ void syrk32_body(const pk_syrk_args &a, float *lds, f
     tj.load(a, j0, 0, tid, stat[0]);
     if (!diag)
         tk.load(a, k0, 0, tid, stat[2]);
-    if (STAGES == 2) {
+    if (GST == 2) {
         tj.store(jt(0), tid, stat[0], stat[1]);
         if (!diag)
             tk.store(kt_(0), tid, stat[2], stat[3]);
@@ -351,8 +354,8 @@ __device__ __forceinline__ void syrk32_body(const pk_syrk_args &a, float *lds, f
     }
 
     for (int64_t kt = 0; kt < nk; ++kt) {
-        const int cur = (STAGES == 2) ? (int)(kt & 1) : 0;
-        if (STAGES == 1) {
+        const int cur = (GST == 2) ? (int)(kt & 1) : 0;
+        if (GST == 1) {
             tj.store(jt(0), tid, stat[0], stat[1]);
             if (!diag)
                 tk.store(kt_(0), tid, stat[2], stat[3]);
@@ -380,7 +383,7 @@ __device__ __forceinline__ void syrk32_body(const pk_syrk_args &a, float *lds, f
                 for (int j = 0; j < FN; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i], fb[j], acc[i][j], 0, 0, 0);
         }
-        if (STAGES == 2 && kt + 1 < nk) {
+        if (GST == 2 && kt + 1 < nk) {
             // registers hold tile kt+1: write it to the other stage (its last
             // readers finished before the previous barrier), fetch tile kt+2
             tj.store(jt(cur ^ 1), tid, stat[0], stat[1]);
@@ -420,7 +423,14 @@ extern "C" __global__ void __launch_bounds__(NT) pk_syrk(pk_syrk_args a) {
     if (blockDim.x != NT)
         return;
     __shared__ __attribute__((aligned(16))) float lds[LDS_FLOATS];
+#if IL == 3
+    // the statistics in the second stage: the general loop (edge tiles) uses the first
+    // only, and the interleaved loop reads them into registers before it first writes
+    // the second (after a barrier), so the two stages are the block's whole LDS
+    float (*stat)[BT] = reinterpret_cast<float (*)[BT]>(lds + 2 * TILE);
+#else
     __shared__ float stat[4][BT];   // mean and 1/std of the j columns, then of the k columns
+#endif
     if (VEC > 1 && a.aligned)
         syrk32_body<VEC>(a, lds, stat);
     else

@@ -359,7 +359,10 @@ def _syrk32_grid():
     rasters."""
     return [dict(BT=bt, BK=bk, WAVES_M=wm, WAVES_N=wn, VEC=4, STAGES=2, ORDER=order, IL=il)
             for il in (1, 2) for bt in (32, 64, 96, 128) for bk in (16, 32, 64, 128)
-            for wm, wn in ((1, 1), (1, 2), (2, 1), (2, 2), (2, 4), (4, 2), (4, 4)) for order in (0, 2)]
+            for wm, wn in ((1, 1), (1, 2), (2, 1), (2, 2), (2, 4), (4, 2), (4, 4)) for order in (0, 2)] + \
+        [dict(BT=bt, BK=bk, WAVES_M=wm, WAVES_N=wn, VEC=4, STAGES=2, ORDER=order, IL=3)
+         for bt in (32, 64) for bk in (16, 32)
+         for wm, wn in ((1, 1), (1, 2), (2, 1), (2, 2), (2, 4), (4, 2), (4, 4)) for order in (0, 2)]
 
 
 def _gemm32_grid():

@@ -58,7 +58,7 @@ REFINE_ONLY = {
     "conv3d": dict(PF=[1, 2], NTL=[0, 1]),
     "gemm_bf16_ws": dict(EPI=[0, 1]),
     "gemm_split_ws": dict(EPI=[0, 1]),
-    "syrk_f32": dict(IL=[0, 1, 2]),
+    "syrk_f32": dict(IL=[0, 1, 2, 3]),
 }
 
 # the reduced-precision contractions: bf16 fragments need BK in multiples of 32

@@ -109,6 +109,9 @@ VARIANTS = [
     ("syrk_f32", dict(BT=32, BK=128, WAVES_M=2, WAVES_N=2, VEC=4, STAGES=2, ORDER=0, IL=1), "default<O3>"),
     ("syrk_f32", dict(BT=32, BK=64, WAVES_M=2, WAVES_N=2, VEC=4, STAGES=2, ORDER=0, IL=2), "default<O3>"),
     ("syrk_f32", dict(BT=64, BK=16, WAVES_M=2, WAVES_N=2, VEC=4, STAGES=2, ORDER=2, IL=2), "default<O3>"),
+    # ... with the column statistics in the second LDS stage (edge tiles: the one-stage loop)
+    ("syrk_f32", dict(BT=64, BK=16, WAVES_M=2, WAVES_N=2, VEC=4, STAGES=2, ORDER=2, IL=3), "default<O3>"),
+    ("syrk_f32", dict(BT=32, BK=32, WAVES_M=1, WAVES_N=2, VEC=4, STAGES=2, ORDER=0, IL=3), "default<O3>"),
     ("conv2d", dict(VEC=4, TX=64, TY=4, ROWS=4, ORDER=2), "default<O3>"),
     # the bf16 / split-bf16 GEMM kernel: tile shapes, one and two LDS stages, scalar loads
     ("gemm_bf16", dict(BM=128, BN=128, BK=64, WAVES_M=2, WAVES_N=2, VEC=4, STAGES=2, ORDER=0), "default<O3>"),

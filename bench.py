@@ -329,8 +329,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py measures one GPU only (asked for {max(args.gpus, world)}); multi-GPU runs are "
-              "not part of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {max(args.gpus, world)}); the kernels run on one "
+              "GPU's share of the work, and no multi-GPU path is measured", file=sys.stderr)
         sys.exit(2)
 
     if args.calibrate_copy:

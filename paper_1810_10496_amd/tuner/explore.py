@@ -505,6 +505,15 @@ def refine(family, workdir, table_path, grid, sizes=(256, 512, 1000, 2048, 4096)
     return changed
 
 
+def upgrade_accepts(t_cur, t_new, margin, gain):
+    """Whether a rebuilt entry (t_new ms) replaces the entry (t_cur ms): both timed (a size
+    without a workload times as inf), and not slower by more than `margin` (a capability)
+    or, with `gain`, faster by at least `margin` (a knob that is there for speed alone)."""
+    if not (math.isfinite(t_cur) and math.isfinite(t_new)):
+        return False
+    return t_new <= t_cur * ((1.0 - margin) if gain else (1.0 + margin))
+
+
 def upgrade(family, workdir, table_path, extra, sizes=(256, 512, 1000, 2048, 4096), replays=30, seeds=30,
             eval_timeout=300.0, log=print, margin=0.03, jobs=8, tag="upgraded", gain=False):
     """Rebuild each non-default table entry with the knobs `extra` added, keeping its
@@ -559,8 +568,7 @@ def upgrade(family, workdir, table_path, extra, sizes=(256, 512, 1000, 2048, 409
                           eval_timeout, replays=replays, validate=False)
             t_cur, t_new = c["times"].get(key, math.inf), n["times"].get(key, math.inf)
             log(f"[upgrade] {family}/{size}: entry {t_cur:.4f} ms, with {extra} {t_new:.4f} ms")
-            if not (math.isfinite(t_cur) and math.isfinite(t_new)) or \
-                    not t_new <= t_cur * ((1.0 - margin) if gain else (1.0 + margin)):
+            if not upgrade_accepts(t_cur, t_new, margin, gain):
                 continue
             val = _evaluate(ev, db, family, rec["sha"], _co_path(workdir, family, rec["sha"]), [], None,
                             eval_timeout, validate=True, seeds=seeds)

@@ -542,3 +542,15 @@ def test_table_report_matches_the_table():
     from paper_1810_10496_amd.tuner.study import table_report
     path = os.path.join(os.path.dirname(tuned.TABLE), "table.md")
     assert open(path).read() == table_report(tuned.TABLE)
+
+
+def test_upgrade_acceptance_rule():
+    from paper_1810_10496_amd.tuner.explore import upgrade_accepts
+    inf = float("inf")
+    # a capability: taken unless slower by more than the margin
+    assert upgrade_accepts(1.0, 1.02, 0.03, gain=False) and not upgrade_accepts(1.0, 1.04, 0.03, gain=False)
+    # a speed knob: taken only when faster by the margin
+    assert upgrade_accepts(1.0, 0.96, 0.03, gain=True) and not upgrade_accepts(1.0, 0.98, 0.03, gain=True)
+    # sizes without a workload time as inf on both sides: never taken
+    assert not upgrade_accepts(inf, inf, 0.03, gain=True) and not upgrade_accepts(inf, inf, 0.03, gain=False)
+    assert not upgrade_accepts(1.0, inf, 0.03, gain=False) and not upgrade_accepts(inf, 0.5, 0.03, gain=True)
